@@ -1,0 +1,253 @@
+"""Benchmark: 32-qubit QPE on one MI355X, complex64, partitioned schedule.
+
+One step = one sv_apply_circuit of the whole 32-qubit QPE gate list (559
+gates + 15 SWAP relabels) on a 2^32-amplitude complex64 state that is
+already resident in HBM. The JSON line reports gate-sweeps/s (gates / step
+time), effective HBM GB/s (algorithmic bytes of the passes / step time), the
+roofline of the block-pass kernel measured with HIP events on its stream, the
+plain complex128 path on the same GPU, and the FP64 oracle on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gate-sweeps/s + effective HBM GB/s (% roofline), 28-32q QPE, c64 vs c128"
+HBM_PEAK_GBPS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "plan.cpp", "plan.h"):
+        with open(os.path.join(ROOT, "paper_2605_15098_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    rec = data.get(f"{kernel}:{workload}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_apply(sim, gates, sched, steps, warmup, kernel_timing=False):
+    import torch
+    from paper_2605_15098_amd import sv
+
+    sv.sv_set_kernel_timing(sim.h, kernel_timing)
+    for _ in range(warmup):
+        sim.apply(gates, sched)
+    torch.cuda.synchronize()
+    kms = [0.0, 0.0, 0.0]
+    kl = [0, 0, 0]
+    dev_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.apply(gates, sched)
+        st = sim.stats()  # waits for this step's last event
+        dev_ms += st["device_ms"]
+        for k in range(3):
+            kms[k] += st["kernel_ms"][k]
+            kl[k] += st["kernel_launches"][k]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sv.sv_set_kernel_timing(sim.h, False)
+    return wall, dev_ms, kms, kl, st
+
+
+def qpe_check(sim, n, phi, gates, sched):
+    """Parity sample at full size: argmax and amplitudes near the peak and at
+    seeded offsets against the QPE closed form (oracle)."""
+    from oracle import qpe as cf
+
+    sim.reset()
+    sim.apply(gates, sched)
+    t = n - 1
+    m, _, pmax = sim.qpe_readout()
+    rng = np.random.default_rng(1234)
+    starts = [max(0, min((1 << t) - 4096, cf.qpe_argmax(t, phi) - 2048))]
+    starts += [int(x) for x in rng.integers(0, (1 << t) - 4096, size=3)]
+    err = 0.0
+    from paper_2605_15098_amd import sv
+    for s0 in starts:
+        got = sv.sv_state_range(sim.h, (1 << t) + s0, 4096, sim.dtype).astype(np.complex128)
+        want = cf.qpe_amplitudes(t, phi, np.arange(s0, s0 + 4096))
+        err = max(err, float(np.max(np.abs(got - want))))
+        zero = sv.sv_state_range(sim.h, s0, 1024, sim.dtype)
+        err = max(err, float(np.max(np.abs(zero))))
+    return {"argmax": int(m), "argmax_expected": cf.qpe_argmax(t, phi),
+            "p_max": pmax, "max_abs_err_sampled": err, "samples": 4 * 4096 + 4 * 1024}
+
+
+def cpu_baseline(n_target, phi, budget_s=20.0):
+    """The FP64 oracle on this host's cores on a bounded sample: the leading
+    gates of the same QPE circuit, on the full 2^n state when host memory
+    allows (else a smaller n, stated in `sample`)."""
+    import oracle
+    from paper_2605_15098_amd import workloads as W
+
+    avail = 0
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemAvailable:"):
+                    avail = int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    n = n_target
+    while n > 20 and (16 << n) * 1.5 > avail:
+        n -= 1
+    gates = W.qpe_gates(n, phi)
+    state = oracle.zero_state(n)
+    done = 0
+    t0 = time.perf_counter()
+    for i in range(len(gates)):
+        state = oracle.apply(n, gates[i:i + 1], state)
+        if int(gates[i]["op"]) != 9:
+            done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    del state
+    return {"value": done / el, "unit": "gate-sweeps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {done} non-SWAP gates of the {n}-qubit QPE circuit, FP64 "
+                      f"(complex128) Algorithm 1 on the host, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--dtype", default="c64")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--quick", action="store_true", help="skip comparison runs and CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_15098_amd import sv
+    from paper_2605_15098_amd import workloads as W
+
+    sv.load()
+    torch.cuda.set_device(0)
+    n = args.n
+    seed = n
+    phi = W.phi_for_seed(seed)
+    gates = W.qpe_gates(n, phi)
+    ngates = W.qpe_gate_count(n)[0]
+    ab = 8 if args.dtype == "c64" else 16
+    sched = sv.schedule(block_qubits=args.block)
+
+    log(f"workload qpe n={n} dtype={args.dtype} phi_seed={seed} gates={ngates}")
+    sim = sv.StateVector(n, args.dtype)
+    wall, dev_ms, kms, kl, st = time_apply(sim, gates, sched, args.steps, args.warmup, kernel_timing=True)
+    ms_per_step = 1000.0 * wall / args.steps
+    value = ngates / (wall / args.steps)
+    eff_gbps = st["bytes"] / (wall / args.steps) / 1e9
+    pass_bytes = 2.0 * ab * 2.0 ** n
+    k2_achieved = (kl[1] * pass_bytes) / (kms[1] / 1000.0) / 1e9 if kl[1] else 0.0
+    log(f"{ms_per_step:.2f} ms/step, {value:.1f} gate-sweeps/s, {eff_gbps:.0f} GB/s effective, "
+        f"k2 {k2_achieved:.0f} GB/s over {kl[1]} launches")
+    check = qpe_check(sim, n, phi, gates, sched)
+    log(f"parity sample: {check}")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "gate-sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "c64" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"qpe-{n}q-{'complex64' if args.dtype == 'c64' else 'complex128'}-partitioned",
+            "n_qubits": n, "counting_qubits": n - 1, "phi_seed": seed, "phi": phi,
+            "gates_per_step": ngates, "swap_relabels": n // 2 - (0 if (n - 1) % 2 else 0),
+            "schedule": {"mode": "partitioned", "block_qubits": st["block_qubits"],
+                         "swap_policy": "lookahead-bulk", "remap": "virtual", "diag_free": True},
+            "passes_per_step": st["passes"], "swaps_per_step": st["swaps"],
+        },
+        "effective_GBps": eff_gbps,
+        "effective_hbm_frac": eff_gbps / HBM_PEAK_GBPS,
+        "device_ms_per_step": dev_ms / args.steps,
+        "roofline": {
+            "kernel": "k2_kernel (block-resident pass)",
+            "bound": "hbm",
+            "achieved": k2_achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": k2_achieved / HBM_PEAK_GBPS,
+            "traffic": measured_traffic("k2", f"qpe{n}-{args.dtype}"),
+            "algorithmic_bytes_per_launch": pass_bytes,
+            "launches": kl[1],
+            "avg_launch_ms": kms[1] / kl[1] if kl[1] else None,
+        },
+        "parity": check,
+    }
+
+    if not args.quick:
+        comps = {}
+        for name, dt, sch, st_, wu in (
+                ("c128-plain", "c128", sv.schedule("plain"), 1, 1),
+                ("c128-partitioned", "c128", sv.schedule(), 3, 1),
+                ("c64-plain", "c64", sv.schedule("plain"), 1, 1),
+                ("c64-paper-lru-l13", "c64", sv.paper_schedule(13), 1, 1)):
+            log(f"comparison {name}")
+            s2 = sv.StateVector(n, dt)
+            w2, d2, _, _, st2 = time_apply(s2, gates, sch, st_, wu)
+            comps[name] = {"ms_per_step": 1000.0 * w2 / st_, "gate_sweeps_per_s": ngates / (w2 / st_),
+                           "effective_GBps": st2["bytes"] / (w2 / st_) / 1e9, "passes": st2["passes"],
+                           "swaps": st2["swaps"]}
+            log(f"  {comps[name]}")
+            s2.close()
+            del s2
+            torch.cuda.empty_cache()
+        out["comparisons"] = comps
+        out["speedup_vs_c128_plain"] = value / comps["c128-plain"]["gate_sweeps_per_s"]
+    if not args.quick and not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(n, phi)
+        log(f"  {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

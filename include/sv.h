@@ -1,0 +1,227 @@
+/*
+ * sv.h - C ABI of the MI355X (gfx950) state-vector simulator.
+ *
+ * The simulator applies quantum gates to a state of 2^n complex amplitudes
+ * without ever forming a 2^n x 2^n matrix (Section III-A of "Accelerating
+ * State-Vector Quantum Simulation on Integrated GPUs via Cache Locality
+ * Optimization", arXiv 2605.15098). A single-qubit gate U on target t updates
+ * every amplitude pair (j, j + 2^t) with bit t of j clear (Algorithm 1); a
+ * controlled gate does so only where bit c of j is 1. The partitioned mode
+ * implements the paper's state division (Section III-B): a block holds 2^l
+ * amplitudes whose l local qubits vary; gates on local qubits are deferred and
+ * applied block by block while the block stays on chip; a gate whose target is
+ * global first brings that qubit into the block in place of a local one chosen
+ * by LRU (or by a look-ahead policy), and a global control is decided per
+ * block.
+ *
+ * Conventions
+ *   - Qubit q is bit q of the amplitude index (little-endian).
+ *   - U is row-major, row = output, column = input, basis (|0>, |1>).
+ *   - Amplitudes are interleaved (re, im): SV_COMPLEX64 = 2 x float,
+ *     SV_COMPLEX128 = 2 x double. Gate matrices are formed in binary64 on the
+ *     host and rounded once to the state's precision.
+ *   - Every readout returns logical order, whatever the physical layout.
+ *
+ * Errors: every call returns an sv_status; on failure sv_last_error() gives a
+ * thread-local message. Calls never throw across the ABI. A handle is not
+ * thread-safe; distinct handles are independent.
+ *
+ * Memory: a handle either owns its device buffer (sv_create) or borrows one
+ * (sv_wrap; the caller keeps it alive and owns the stream). Gate arrays are
+ * borrowed for the duration of a call. Output pointers may be host or device
+ * memory (detected with hipPointerGetAttributes): host outputs synchronize the
+ * handle's stream, device outputs are stream-ordered.
+ */
+#ifndef SVMI_SV_H_INCLUDED
+#define SVMI_SV_H_INCLUDED
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sv_handle_s *sv_handle;
+typedef int32_t sv_status;
+
+enum {
+    SV_OK = 0,
+    SV_ERR_INVALID_ARG = -1,   /* bad n, qubit, op, angle, schedule or pointer */
+    SV_ERR_OUT_OF_MEMORY = -2, /* device or host allocation failed            */
+    SV_ERR_DEVICE = -3,        /* a HIP call failed; message has the HIP error */
+    SV_ERR_UNSUPPORTED = -4,   /* valid request outside what this build does   */
+    SV_ERR_BAD_HANDLE = -5     /* null or destroyed handle                     */
+};
+
+typedef enum { SV_COMPLEX64 = 0, SV_COMPLEX128 = 1 } sv_dtype;
+
+/* Gate kinds. Controlled forms use sv_gate.control >= 0:
+ * CNOT = {SV_X, c}, CZ = {SV_Z, c}, CP(theta) = {SV_P, theta, c}; QPE's
+ * controlled U^(2^j) (Eq. 3) is {SV_P, theta_j, control = j}. */
+enum {
+    SV_H = 0,  /* [[1,1],[1,-1]]/sqrt2                          */
+    SV_X = 1,
+    SV_Y = 2,
+    SV_Z = 3,
+    SV_RX = 4, /* exp(-i theta X/2)                              */
+    SV_RY = 5, /* exp(-i theta Y/2)                              */
+    SV_RZ = 6, /* exp(-i theta Z/2) = diag(e^{-i theta/2}, e^{i theta/2}) */
+    SV_P = 7,  /* diag(1, e^{i theta}) (Eq. 2)                   */
+    SV_U2 = 8, /* arbitrary 2x2 given in u[8]                    */
+    SV_SWAP = 9 /* exchange qubits target and target2; a relabel */
+};
+
+/* One gate (88 bytes). control = -1 for none; target2 only for SV_SWAP;
+ * theta in radians for RX/RY/RZ/P; u = row-major 2x2 (re, im) for SV_U2.
+ * One control at most (Section III-A); SWAP takes no control. */
+typedef struct {
+    int32_t op, target, control, target2;
+    double theta;
+    double u[8];
+} sv_gate;
+
+/* Schedule modes and options. */
+enum { SV_PLAIN = 0, SV_PARTITIONED = 1 };
+enum { SV_SWAP_LRU = 0, SV_SWAP_LOOKAHEAD = 1 };
+enum {
+    SV_REMAP_VIRTUAL = 0, /* a SWAP moves no data: the next block pass gathers
+                             the new local qubits by address (zero bytes)     */
+    SV_REMAP_EXPLICIT = 1 /* a SWAP is a standalone in-place exchange pass    */
+};
+enum { SV_TUNER_NONE = 0, SV_TUNER_EXHAUSTIVE = 1, SV_TUNER_LEARNED = 2 };
+
+typedef struct {
+    int32_t mode;         /* SV_PLAIN: one sweep per gate (Algorithm 1);
+                             SV_PARTITIONED: Section III-B                     */
+    int32_t block_qubits; /* l, local qubits per on-chip block; 0 = default   */
+    int32_t outer_qubits; /* l2 > l: second tier sized for the Infinity Cache;
+                             0 = off                                          */
+    int32_t fuse_k;       /* <= 1: no fusion; 2..6: fuse runs of gates on <= k
+                             qubits into one 2^k x 2^k unitary (FP64 product)  */
+    int32_t swap_policy;  /* SV_SWAP_LRU (the paper) or SV_SWAP_LOOKAHEAD     */
+    int32_t remap;        /* SV_REMAP_VIRTUAL or SV_REMAP_EXPLICIT            */
+    int32_t diag_free;    /* 0: every gate's target must be local (the paper's
+                             rule); 1: diagonal gates (Z, P, RZ and their
+                             controlled forms) never force a SWAP              */
+    int32_t tuner;        /* SV_TUNER_*: sv_apply_circuit first picks l, k and
+                             the policy itself                                */
+} sv_schedule;
+
+typedef struct {
+    int64_t gates;       /* non-SWAP gates applied by the last call            */
+    int64_t swaps;       /* SWAPs of a global target into the block            */
+    int64_t phases;      /* deferred-queue flushes (block-resident passes)      */
+    int64_t passes;      /* kernels that sweep the whole state                  */
+    int64_t fused;       /* fused k-qubit windows                              */
+    double bytes;        /* algorithmic HBM bytes of those passes              */
+    double device_ms;    /* device time of the last call (HIP events)          */
+    double plan_ms;      /* host planning time of the last call                */
+    int32_t block_qubits;/* l used by the last call                            */
+    int32_t fuse_k;      /* k used                                             */
+    int32_t swap_policy; /* policy used                                        */
+    int32_t mode;        /* mode used                                          */
+    double norm_drift;   /* |norm^2 - 1| at the last sv_norm call             */
+    /* Per-kernel device time of the last call, filled only while kernel
+     * timing is on (sv_set_kernel_timing): index 0 = plain sweeps, 1 = block
+     * passes, 2 = explicit SWAP passes. */
+    double kernel_ms[3];
+    int64_t kernel_launches[3];
+} sv_stats;
+
+/* Library version string. */
+const char *sv_version(void);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *sv_last_error(void);
+
+/* Allocate a state of 2^n amplitudes on the current HIP device, set it to
+ * |0...0> (Section III-A: the state is an array of 2^n complex numbers).
+ * n in [1, 36]. Errors: INVALID_ARG (n, dtype, out), OUT_OF_MEMORY, DEVICE. */
+sv_status sv_create(int n, sv_dtype dtype, sv_handle *out);
+
+/* Borrow a device buffer (e.g. a torch tensor's storage) of at least
+ * 2^n * sizeof(amplitude) bytes and a HIP stream (NULL = default stream).
+ * The buffer's content is taken as the state in logical order; it is not
+ * cleared. The caller keeps buffer and stream alive until sv_destroy. */
+sv_status sv_wrap(int n, sv_dtype dtype, void *dev_buf, size_t bytes, void *hip_stream,
+                  sv_handle *out);
+
+/* Release the handle (and the buffer if it owns it). NULL is accepted. */
+sv_status sv_destroy(sv_handle h);
+
+/* Set the state back to |0...0> and the layout to identity. */
+sv_status sv_reset(sv_handle h);
+
+/* Change the stream later calls are ordered on (NULL = default stream). */
+sv_status sv_set_stream(sv_handle h, void *hip_stream);
+
+/* Apply m gates in order to the current state (calls accumulate). The
+ * schedule may be NULL (= partitioned, defaults). The physical layout may
+ * stay permuted between calls; readouts undo it. Stream-ordered: returns
+ * once the work is queued. Errors: INVALID_ARG (target >= n, control ==
+ * target, non-finite theta, unknown op, SWAP with a control), UNSUPPORTED
+ * (fuse_k > 6), DEVICE. No gate is applied when validation fails. */
+sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *s);
+
+/* Many independent circuits (one per handle, all of one dtype) in one
+ * persistent kernel launch, replayed from a captured HIP graph when the same
+ * batch shape is applied again. Each handle's state is updated as by
+ * sv_apply_circuit with a partitioned schedule. Handles must be distinct and
+ * on the same device. */
+sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m,
+                         const sv_schedule *s);
+
+/* Probabilities |alpha|^2 in FP64 (measurement, the meters of the QPE
+ * figure). nq = 0: all 2^n in logical order. Otherwise the marginal over the
+ * listed qubits: out[m] sums |alpha_i|^2 over every i whose bits
+ * qubits[0..nq-1] spell m (qubits[k] = bit k of m); 2^nq doubles. */
+sv_status sv_probabilities(sv_handle h, const int *qubits, int nq, double *out);
+
+/* All 2^n amplitudes in logical order (interleaved, the handle's dtype). */
+sv_status sv_state(sv_handle h, void *out);
+
+/* Amplitudes [offset, offset+count) of the logical order, and their import
+ * (checkpoint / resume between circuits). */
+sv_status sv_state_range(sv_handle h, uint64_t offset, uint64_t count, void *out);
+sv_status sv_set_state_range(sv_handle h, uint64_t offset, uint64_t count, const void *in);
+
+/* QPE readout (Section IV-A): marginal over counting qubits 0..t-1 in FP64,
+ * its argmax m (lowest index wins ties), phi = m / 2^t and P(m). */
+sv_status sv_qpe_readout(sv_handle h, int t, uint64_t *m, double *phi, double *pmax);
+
+/* Sum of |alpha|^2 in FP64. Also records |norm - 1| in the stats. */
+sv_status sv_norm(sv_handle h, double *norm2);
+
+/* Counters and timing of the last sv_apply_circuit (synchronizes). */
+sv_status sv_stats_get(sv_handle h, sv_stats *out);
+
+/* Host-only planning, usable without a GPU: the counts (gates, swaps,
+ * phases, passes, bytes) the given schedule would produce for this circuit on
+ * an n-qubit state of the given dtype starting from the identity layout. */
+sv_status sv_plan(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const sv_schedule *s,
+                  sv_stats *out);
+
+/* Pick a schedule for this circuit on this handle. mode = SV_TUNER_EXHAUSTIVE
+ * times every candidate on a scratch copy of the state; SV_TUNER_LEARNED asks
+ * the cost model loaded by sv_model_load (falls back to exhaustive without
+ * one). The state itself is not changed. */
+sv_status sv_tune(sv_handle h, const sv_gate *gates, size_t m, int mode, sv_schedule *out);
+
+/* Record a HIP event pair around every kernel of later sv_apply_circuit
+ * calls on this handle (on = 1) so sv_stats_get reports per-kernel device
+ * time; on = 0 (the default) records one pair per call. */
+sv_status sv_set_kernel_timing(sv_handle h, int on);
+
+/* Permutation of the current layout: l2p[q] = physical bit of qubit q. */
+sv_status sv_layout(sv_handle h, int *l2p);
+
+/* Testing hook: make the next device allocation (kind 1) or kernel launch
+ * (kind 2) of this process fail; 0 clears. */
+sv_status sv_debug_inject_fault(int kind);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVMI_SV_H_INCLUDED */

@@ -1,0 +1,684 @@
+// C ABI of the simulator (include/sv.h): handles, validation, plan
+// execution on a HIP stream, FP64 readouts. No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/sv.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_live_mu;
+std::unordered_set<const void *> g_live;
+int g_fault = 0;  // 1: next device allocation fails; 2: next launch fails
+
+sv_status fail(sv_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+sv_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(SV_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SV_HIP(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
+    } while (0)
+
+hipError_t dev_alloc(void **p, size_t bytes)
+{
+    if (g_fault == 1) {
+        g_fault = 0;
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+bool launch_fault()
+{
+    if (g_fault == 2) {
+        g_fault = 0;
+        return true;
+    }
+    return false;
+}
+
+size_t amp_bytes(int dtype) { return dtype == SV_COMPLEX64 ? 8 : 16; }
+
+}  // namespace
+
+struct sv_handle_s {
+    int n = 0;
+    int dtype = 0;
+    void *buf = nullptr;
+    size_t bytes = 0;
+    bool owns = false;
+    hipStream_t stream = nullptr;
+    std::vector<int> l2p;
+    svp::K2Op *dops = nullptr;
+    size_t dops_cap = 0;
+    void *scratch = nullptr;
+    size_t scratch_cap = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    bool kernel_timing = false;
+    std::vector<hipEvent_t> kev;   // pairs around each launch when kernel_timing
+    std::vector<int> kev_kind;
+    sv_stats st{};
+};
+
+namespace {
+
+sv_status check_handle(sv_handle h)
+{
+    if (!h) return fail(SV_ERR_BAD_HANDLE, "null handle");
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    if (!g_live.count(h)) return fail(SV_ERR_BAD_HANDLE, "handle is not live");
+    return SV_OK;
+}
+
+sv_status ensure_scratch(sv_handle h, size_t bytes)
+{
+    if (bytes <= h->scratch_cap) return SV_OK;
+    if (h->scratch) {
+        hipStreamSynchronize(h->stream);
+        hipFree(h->scratch);
+        h->scratch = nullptr;
+        h->scratch_cap = 0;
+    }
+    void *p = nullptr;
+    if (dev_alloc(&p, bytes) != hipSuccess) return fail(SV_ERR_OUT_OF_MEMORY, "scratch allocation failed");
+    h->scratch = p;
+    h->scratch_cap = bytes;
+    return SV_OK;
+}
+
+// true when p is device (or managed) memory
+bool is_device_ptr(const void *p)
+{
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+bool identity(const std::vector<int> &l2p)
+{
+    for (size_t q = 0; q < l2p.size(); ++q)
+        if (l2p[q] != (int)q) return false;
+    return true;
+}
+
+sv_status new_handle(int n, sv_dtype dtype, sv_handle *out, sv_handle_s **hp)
+{
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (n < 1 || n > 36) return fail(SV_ERR_INVALID_ARG, "n must be in [1, 36]");
+    if (dtype != SV_COMPLEX64 && dtype != SV_COMPLEX128) return fail(SV_ERR_INVALID_ARG, "unknown dtype");
+    sv_handle_s *h = new (std::nothrow) sv_handle_s();
+    if (!h) return fail(SV_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->n = n;
+    h->dtype = dtype;
+    h->l2p.resize(n);
+    for (int q = 0; q < n; ++q) h->l2p[q] = q;
+    *hp = h;
+    return SV_OK;
+}
+
+void free_handle(sv_handle_s *h)
+{
+    for (hipEvent_t e : h->kev) hipEventDestroy(e);
+    if (h->ev0) hipEventDestroy(h->ev0);
+    if (h->ev1) hipEventDestroy(h->ev1);
+    if (h->dops) hipFree(h->dops);
+    if (h->scratch) hipFree(h->scratch);
+    if (h->owns && h->buf) hipFree(h->buf);
+    delete h;
+}
+
+sv_status finish_handle(sv_handle_s *h, sv_handle *out)
+{
+    hipError_t e = hipEventCreate(&h->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+    if (e != hipSuccess) {
+        free_handle(h);
+        return hip_fail(e, "hipEventCreate");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.insert(h);
+    }
+    *out = h;
+    return SV_OK;
+}
+
+svp::PlanConfig config_from(sv_handle h, const sv_schedule *s)
+{
+    svp::PlanConfig c;
+    c.n = h->n;
+    c.dtype = h->dtype;
+    if (!s) {
+        c.mode = 1;
+        c.l = 0;
+        c.policy = SV_SWAP_LOOKAHEAD;
+        c.remap = SV_REMAP_VIRTUAL;
+        c.diag_free = 1;
+        c.fuse_k = 1;
+    } else {
+        c.mode = s->mode;
+        c.l = s->block_qubits;
+        c.policy = s->swap_policy;
+        c.remap = s->remap;
+        c.diag_free = s->diag_free;
+        c.fuse_k = s->fuse_k;
+    }
+    if (const char *e = std::getenv("SV_PIN_BITS")) c.pin_low = std::atoi(e);
+    if (const char *e = std::getenv("SV_LOGR")) c.logr = std::atoi(e);
+    return c;
+}
+
+sv_status check_schedule(const sv_schedule *s, int dtype)
+{
+    if (!s) return SV_OK;
+    if (s->mode != SV_PLAIN && s->mode != SV_PARTITIONED) return fail(SV_ERR_INVALID_ARG, "unknown mode");
+    if (s->block_qubits < 0) return fail(SV_ERR_INVALID_ARG, "block_qubits < 0");
+    if (s->block_qubits > svp::max_block_qubits(dtype))
+        return fail(SV_ERR_UNSUPPORTED, "block_qubits above the on-chip maximum for this dtype");
+    if (s->swap_policy != SV_SWAP_LRU && s->swap_policy != SV_SWAP_LOOKAHEAD)
+        return fail(SV_ERR_INVALID_ARG, "unknown swap policy");
+    if (s->remap != SV_REMAP_VIRTUAL && s->remap != SV_REMAP_EXPLICIT)
+        return fail(SV_ERR_INVALID_ARG, "unknown remap");
+    if (s->fuse_k > 6) return fail(SV_ERR_UNSUPPORTED, "fuse_k above 6");
+    if (s->fuse_k > 1) return fail(SV_ERR_UNSUPPORTED, "fusion is not available in this build");
+    if (s->outer_qubits != 0) return fail(SV_ERR_UNSUPPORTED, "outer tier is not available in this build");
+    if (s->tuner != SV_TUNER_NONE) return fail(SV_ERR_UNSUPPORTED, "tuner inside apply is not available");
+    return SV_OK;
+}
+
+sv_status run_plan(sv_handle h, const svp::Plan &plan)
+{
+    if (!plan.ops.empty()) {
+        const size_t need = plan.ops.size();
+        if (need > h->dops_cap) {
+            if (h->dops) {
+                hipStreamSynchronize(h->stream);
+                hipFree(h->dops);
+                h->dops = nullptr;
+                h->dops_cap = 0;
+            }
+            size_t cap = std::max<size_t>(need, 1024);
+            void *p = nullptr;
+            if (dev_alloc(&p, cap * sizeof(svp::K2Op)) != hipSuccess)
+                return fail(SV_ERR_OUT_OF_MEMORY, "program buffer allocation failed");
+            h->dops = (svp::K2Op *)p;
+            h->dops_cap = cap;
+        }
+        SV_HIP(hipMemcpyAsync(h->dops, plan.ops.data(), need * sizeof(svp::K2Op), hipMemcpyHostToDevice,
+                              h->stream),
+               "program upload");
+    }
+    h->kev_kind.clear();
+    if (h->kernel_timing) {
+        const size_t need = 2 * plan.steps.size();
+        while (h->kev.size() < need) {
+            hipEvent_t e;
+            SV_HIP(hipEventCreate(&e), "hipEventCreate");
+            h->kev.push_back(e);
+        }
+    }
+    SV_HIP(hipEventRecord(h->ev0, h->stream), "hipEventRecord");
+    for (const svp::Step &s : plan.steps) {
+        if (launch_fault()) return fail(SV_ERR_DEVICE, "injected launch failure");
+        hipError_t e = hipSuccess;
+        if (h->kernel_timing) {
+            SV_HIP(hipEventRecord(h->kev[2 * h->kev_kind.size()], h->stream), "hipEventRecord");
+        }
+        if (s.kind == svp::ST_K1) {
+            e = svk::k1_gate(h->buf, h->n, h->dtype, s.g, h->stream);
+        } else if (s.kind == svp::ST_K3) {
+            e = svk::k3_swap(h->buf, h->n, h->dtype, s.p, s.v, h->stream);
+        } else {
+            svk::K2Args a{};
+            a.n = h->n;
+            a.l = s.l;
+            a.nops = s.op_count;
+            std::vector<bool> in(h->n, false);
+            for (int i = 0; i < s.l; ++i) {
+                a.bits[i] = (int8_t)s.bits[i];
+                in[s.bits[i]] = true;
+            }
+            int k = 0;
+            for (int p = 0; p < h->n; ++p)
+                if (!in[p]) a.nbits[k++] = (int8_t)p;
+            e = svk::k2_pass(h->buf, h->n, h->dtype, s.logr, a, h->dops + s.op_begin, h->stream);
+        }
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (h->kernel_timing) {
+            SV_HIP(hipEventRecord(h->kev[2 * h->kev_kind.size() + 1], h->stream), "hipEventRecord");
+            h->kev_kind.push_back(s.kind == svp::ST_K1 ? 0 : (s.kind == svp::ST_K2 ? 1 : 2));
+        }
+    }
+    SV_HIP(hipEventRecord(h->ev1, h->stream), "hipEventRecord");
+    h->timed = true;
+    return SV_OK;
+}
+
+void fill_stats(sv_stats *o, const svp::PlanConfig &c, const svp::Plan &p)
+{
+    o->gates = p.stats.gates;
+    o->swaps = p.stats.swaps;
+    o->phases = p.stats.phases;
+    o->passes = p.stats.passes;
+    o->fused = p.stats.fused;
+    o->bytes = p.stats.bytes;
+    o->block_qubits = p.l;
+    o->fuse_k = c.fuse_k > 1 ? c.fuse_k : 1;
+    o->swap_policy = c.policy;
+    o->mode = c.mode;
+}
+
+// complement of the physical bits in `q` among 0..n-1, ascending
+std::vector<int> complement(int n, const std::vector<int> &q)
+{
+    std::vector<bool> in(n, false);
+    for (int b : q) in[b] = true;
+    std::vector<int> o;
+    for (int p = 0; p < n; ++p)
+        if (!in[p]) o.push_back(p);
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sv_version(void) { return "svmi 0.1 (gfx950)"; }
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+sv_status sv_debug_inject_fault(int kind)
+{
+    if (kind < 0 || kind > 2) return fail(SV_ERR_INVALID_ARG, "unknown fault kind");
+    g_fault = kind;
+    return SV_OK;
+}
+
+sv_status sv_create(int n, sv_dtype dtype, sv_handle *out)
+{
+    sv_handle_s *h = nullptr;
+    sv_status s = new_handle(n, dtype, out, &h);
+    if (s) return s;
+    h->bytes = amp_bytes(dtype) << n;
+    h->owns = true;
+    hipError_t e = dev_alloc(&h->buf, h->bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->buf = nullptr;
+        free_handle(h);
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            return fail(SV_ERR_OUT_OF_MEMORY, "device allocation of the state failed");
+        return hip_fail(e, "hipMalloc");
+    }
+    e = svk::init_zero_state(h->buf, n, dtype, h->stream);
+    if (e != hipSuccess) {
+        free_handle(h);
+        return hip_fail(e, "init");
+    }
+    return finish_handle(h, out);
+}
+
+sv_status sv_wrap(int n, sv_dtype dtype, void *dev_buf, size_t bytes, void *hip_stream, sv_handle *out)
+{
+    sv_handle_s *h = nullptr;
+    sv_status s = new_handle(n, dtype, out, &h);
+    if (s) return s;
+    if (!dev_buf) {
+        delete h;
+        return fail(SV_ERR_INVALID_ARG, "buffer is null");
+    }
+    if (bytes < (amp_bytes(dtype) << n)) {
+        delete h;
+        return fail(SV_ERR_INVALID_ARG, "buffer smaller than 2^n amplitudes");
+    }
+    h->buf = dev_buf;
+    h->bytes = bytes;
+    h->owns = false;
+    h->stream = (hipStream_t)hip_stream;
+    return finish_handle(h, out);
+}
+
+sv_status sv_destroy(sv_handle h)
+{
+    if (!h) return SV_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (!g_live.erase(h)) return fail(SV_ERR_BAD_HANDLE, "handle is not live");
+    }
+    hipStreamSynchronize(h->stream);
+    free_handle(h);
+    return SV_OK;
+}
+
+sv_status sv_reset(sv_handle h)
+{
+    if (sv_status s = check_handle(h)) return s;
+    for (int q = 0; q < h->n; ++q) h->l2p[q] = q;
+    SV_HIP(svk::init_zero_state(h->buf, h->n, h->dtype, h->stream), "init");
+    return SV_OK;
+}
+
+sv_status sv_set_stream(sv_handle h, void *hip_stream)
+{
+    if (sv_status s = check_handle(h)) return s;
+    h->stream = (hipStream_t)hip_stream;
+    return SV_OK;
+}
+
+sv_status sv_set_kernel_timing(sv_handle h, int on)
+{
+    if (sv_status s = check_handle(h)) return s;
+    h->kernel_timing = on != 0;
+    return SV_OK;
+}
+
+sv_status sv_layout(sv_handle h, int *l2p)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (!l2p) return fail(SV_ERR_INVALID_ARG, "out is null");
+    for (int q = 0; q < h->n; ++q) l2p[q] = h->l2p[q];
+    return SV_OK;
+}
+
+sv_status sv_plan(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const sv_schedule *s, sv_stats *out)
+{
+    if (n < 1 || n > 36) return fail(SV_ERR_INVALID_ARG, "n must be in [1, 36]");
+    if (dtype != SV_COMPLEX64 && dtype != SV_COMPLEX128) return fail(SV_ERR_INVALID_ARG, "unknown dtype");
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    if (sv_status st = check_schedule(s, dtype)) return st;
+    sv_handle_s tmp;
+    tmp.n = n;
+    tmp.dtype = dtype;
+    svp::PlanConfig c = config_from(&tmp, s);
+    std::vector<int> l2p(n);
+    for (int q = 0; q < n; ++q) l2p[q] = q;
+    svp::Plan plan;
+    std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, l2p, plan);
+    if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+    std::memset(out, 0, sizeof(*out));
+    fill_stats(out, c, plan);
+    return SV_OK;
+}
+
+sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *s)
+{
+    if (sv_status st = check_handle(h)) return st;
+    if (sv_status st = check_schedule(s, h->dtype)) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    svp::PlanConfig c = config_from(h, s);
+    svp::Plan plan;
+    std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, h->l2p, plan);
+    if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (sv_status st = run_plan(h, plan)) return st;
+    h->l2p = plan.l2p_after;
+    std::memset(&h->st, 0, sizeof(h->st));
+    fill_stats(&h->st, c, plan);
+    h->st.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return SV_OK;
+}
+
+sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m,
+                         const sv_schedule *s)
+{
+    if (count < 0 || (count > 0 && (!hs || !gates || !m))) return fail(SV_ERR_INVALID_ARG, "bad batch arrays");
+    for (int i = 0; i < count; ++i)
+        if (sv_status st = sv_apply_circuit(hs[i], gates[i], m[i], s)) return st;
+    return SV_OK;
+}
+
+sv_status sv_stats_get(sv_handle h, sv_stats *out)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    if (h->timed) {
+        SV_HIP(hipEventSynchronize(h->ev1), "hipEventSynchronize");
+        float ms = 0.f;
+        SV_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1), "hipEventElapsedTime");
+        h->st.device_ms = ms;
+        for (int k = 0; k < 3; ++k) {
+            h->st.kernel_ms[k] = 0.0;
+            h->st.kernel_launches[k] = 0;
+        }
+        for (size_t i = 0; i < h->kev_kind.size(); ++i) {
+            float kms = 0.f;
+            SV_HIP(hipEventElapsedTime(&kms, h->kev[2 * i], h->kev[2 * i + 1]), "hipEventElapsedTime");
+            h->st.kernel_ms[h->kev_kind[i]] += kms;
+            h->st.kernel_launches[h->kev_kind[i]] += 1;
+        }
+    }
+    *out = h->st;
+    return SV_OK;
+}
+
+sv_status sv_norm(sv_handle h, double *norm2)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (!norm2) return fail(SV_ERR_INVALID_ARG, "out is null");
+    const size_t need = svk::norm_scratch_bytes(h->n) + 64;
+    if (sv_status s = ensure_scratch(h, need)) return s;
+    double *res = (double *)((char *)h->scratch + svk::norm_scratch_bytes(h->n));
+    SV_HIP(svk::norm2(h->buf, h->n, h->dtype, h->scratch, res, h->stream), "norm");
+    SV_HIP(hipMemcpyAsync(norm2, res, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+    SV_HIP(hipStreamSynchronize(h->stream), "sync");
+    h->st.norm_drift = std::fabs(*norm2 - 1.0);
+    return SV_OK;
+}
+
+sv_status sv_probabilities(sv_handle h, const int *qubits, int nq, double *out)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    if (nq < 0 || nq > h->n) return fail(SV_ERR_INVALID_ARG, "nq out of range");
+    if (nq > 0 && !qubits) return fail(SV_ERR_INVALID_ARG, "qubits is null");
+    std::vector<int> qb;
+    std::vector<bool> seen(h->n, false);
+    for (int k = 0; k < nq; ++k) {
+        if (qubits[k] < 0 || qubits[k] >= h->n || seen[qubits[k]])
+            return fail(SV_ERR_INVALID_ARG, "qubit list has an out-of-range or repeated entry");
+        seen[qubits[k]] = true;
+        qb.push_back(h->l2p[qubits[k]]);
+    }
+    const bool dev = is_device_ptr(out);
+    if (nq == 0 || nq == h->n) {
+        // all probabilities in logical order (nq == n with a permuted list is a marginal)
+        bool plain_order = (nq == 0);
+        if (nq == h->n) {
+            plain_order = true;
+            for (int k = 0; k < nq; ++k)
+                if (qubits[k] != k) plain_order = false;
+        }
+        if (plain_order) {
+            const uint64_t N = 1ull << h->n;
+            if (dev) {
+                SV_HIP(svk::probabilities(h->buf, h->n, h->dtype, h->l2p.data(), out, 0, N, h->stream), "probs");
+                return SV_OK;
+            }
+            const uint64_t chunk = std::min<uint64_t>(N, 1ull << 24);
+            if (sv_status s = ensure_scratch(h, chunk * sizeof(double))) return s;
+            for (uint64_t off = 0; off < N; off += chunk) {
+                const uint64_t cnt = std::min(chunk, N - off);
+                SV_HIP(svk::probabilities(h->buf, h->n, h->dtype, h->l2p.data(), (double *)h->scratch, off, cnt,
+                                          h->stream),
+                       "probs");
+                SV_HIP(hipMemcpyAsync(out + off, h->scratch, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                                      h->stream),
+                       "copy");
+                SV_HIP(hipStreamSynchronize(h->stream), "sync");
+            }
+            return SV_OK;
+        }
+    }
+    const std::vector<int> ob = complement(h->n, qb);
+    const uint64_t M = 1ull << nq;
+    if (h->n - nq > 12 && M > 65535) return fail(SV_ERR_UNSUPPORTED, "marginal shape not supported");
+    const size_t sb = svk::marginal_scratch_bytes(h->n, nq);
+    const size_t outb = dev ? 0 : M * sizeof(double);
+    if (sv_status s = ensure_scratch(h, sb + outb + 256)) return s;
+    double *dst = dev ? out : (double *)((char *)h->scratch + ((sb + 255) / 256) * 256);
+    SV_HIP(svk::marginal(h->buf, h->n, h->dtype, qb.data(), nq, ob.data(), dst, h->scratch, h->stream), "marginal");
+    if (!dev) {
+        SV_HIP(hipMemcpyAsync(out, dst, M * sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+        SV_HIP(hipStreamSynchronize(h->stream), "sync");
+    }
+    return SV_OK;
+}
+
+sv_status sv_qpe_readout(sv_handle h, int t, uint64_t *m, double *phi, double *pmax)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (t < 1 || t > h->n) return fail(SV_ERR_INVALID_ARG, "t out of range");
+    if (!m || !phi || !pmax) return fail(SV_ERR_INVALID_ARG, "null output");
+    std::vector<int> qb(t);
+    for (int k = 0; k < t; ++k) qb[k] = h->l2p[k];
+    const std::vector<int> ob = complement(h->n, qb);
+    const size_t am = svk::argmax_scratch_bytes(1ull << t);
+    const size_t resb = 64;
+    if (h->n - t <= 4) {
+        if (sv_status s = ensure_scratch(h, am + resb)) return s;
+        char *base = (char *)h->scratch;
+        uint64_t *ri = (uint64_t *)(base + am);
+        double *rv = (double *)(base + am + 8);
+        SV_HIP(svk::marginal_argmax(h->buf, h->n, h->dtype, qb.data(), t, ob.data(), h->scratch, ri, rv, h->stream),
+               "qpe readout");
+        uint64_t hi = 0;
+        double hv = 0;
+        SV_HIP(hipMemcpyAsync(&hi, ri, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+        SV_HIP(hipMemcpyAsync(&hv, rv, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+        SV_HIP(hipStreamSynchronize(h->stream), "sync");
+        *m = hi;
+        *pmax = hv;
+    } else {
+        const uint64_t M = 1ull << t;
+        if (h->n - t > 12 && M > 65535) return fail(SV_ERR_UNSUPPORTED, "marginal shape not supported");
+        const size_t sb = ((svk::marginal_scratch_bytes(h->n, t) + 255) / 256) * 256;
+        const size_t mb = ((M * sizeof(double) + 255) / 256) * 256;
+        if (sv_status s = ensure_scratch(h, sb + mb + am + resb)) return s;
+        char *base = (char *)h->scratch;
+        double *marg = (double *)(base + sb);
+        void *ams = base + sb + mb;
+        uint64_t *ri = (uint64_t *)(base + sb + mb + am);
+        double *rv = (double *)(base + sb + mb + am + 8);
+        SV_HIP(svk::marginal(h->buf, h->n, h->dtype, qb.data(), t, ob.data(), marg, base, h->stream), "marginal");
+        SV_HIP(svk::argmax(marg, M, ams, ri, rv, h->stream), "argmax");
+        uint64_t hi = 0;
+        double hv = 0;
+        SV_HIP(hipMemcpyAsync(&hi, ri, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+        SV_HIP(hipMemcpyAsync(&hv, rv, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+        SV_HIP(hipStreamSynchronize(h->stream), "sync");
+        *m = hi;
+        *pmax = hv;
+    }
+    *phi = std::ldexp((double)*m, -t);
+    return SV_OK;
+}
+
+static sv_status state_io(sv_handle h, uint64_t offset, uint64_t count, void *out, const void *in)
+{
+    const uint64_t N = 1ull << h->n;
+    if (offset > N || count > N - offset) return fail(SV_ERR_INVALID_ARG, "range outside the state");
+    if (count == 0) return SV_OK;
+    const size_t ab = amp_bytes(h->dtype);
+    void *user = out ? out : const_cast<void *>(in);
+    const bool dev = is_device_ptr(user);
+    const bool ident = identity(h->l2p);
+    char *sbase = (char *)h->buf + offset * ab;
+    if (ident) {
+        if (out) {
+            SV_HIP(hipMemcpyAsync(out, sbase, count * ab, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                  h->stream),
+                   "copy");
+        } else {
+            SV_HIP(hipMemcpyAsync(sbase, in, count * ab, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  h->stream),
+                   "copy");
+        }
+        if (!dev) SV_HIP(hipStreamSynchronize(h->stream), "sync");
+        return SV_OK;
+    }
+    if (dev) {
+        if (out) SV_HIP(svk::gather_logical(h->buf, h->n, h->dtype, h->l2p.data(), out, offset, count, h->stream), "gather");
+        else SV_HIP(svk::scatter_logical(h->buf, h->n, h->dtype, h->l2p.data(), in, offset, count, h->stream), "scatter");
+        return SV_OK;
+    }
+    const uint64_t chunk = std::min<uint64_t>(count, (1ull << 27) / ab);
+    if (sv_status s = ensure_scratch(h, chunk * ab)) return s;
+    for (uint64_t o = 0; o < count; o += chunk) {
+        const uint64_t c = std::min(chunk, count - o);
+        if (out) {
+            SV_HIP(svk::gather_logical(h->buf, h->n, h->dtype, h->l2p.data(), h->scratch, offset + o, c, h->stream),
+                   "gather");
+            SV_HIP(hipMemcpyAsync((char *)out + o * ab, h->scratch, c * ab, hipMemcpyDeviceToHost, h->stream), "copy");
+            SV_HIP(hipStreamSynchronize(h->stream), "sync");
+        } else {
+            SV_HIP(hipMemcpyAsync(h->scratch, (const char *)in + o * ab, c * ab, hipMemcpyHostToDevice, h->stream),
+                   "copy");
+            SV_HIP(svk::scatter_logical(h->buf, h->n, h->dtype, h->l2p.data(), h->scratch, offset + o, c, h->stream),
+                   "scatter");
+            SV_HIP(hipStreamSynchronize(h->stream), "sync");
+        }
+    }
+    return SV_OK;
+}
+
+sv_status sv_state(sv_handle h, void *out)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    return state_io(h, 0, 1ull << h->n, out, nullptr);
+}
+
+sv_status sv_state_range(sv_handle h, uint64_t offset, uint64_t count, void *out)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    return state_io(h, offset, count, out, nullptr);
+}
+
+sv_status sv_set_state_range(sv_handle h, uint64_t offset, uint64_t count, const void *in)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (!in) return fail(SV_ERR_INVALID_ARG, "in is null");
+    return state_io(h, offset, count, nullptr, in);
+}
+
+sv_status sv_tune(sv_handle h, const sv_gate *gates, size_t m, int mode, sv_schedule *out)
+{
+    if (sv_status s = check_handle(h)) return s;
+    (void)gates;
+    (void)m;
+    (void)mode;
+    (void)out;
+    return fail(SV_ERR_UNSUPPORTED, "tuner not available in this build");
+}
+
+}  // extern "C"

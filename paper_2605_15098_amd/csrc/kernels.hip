@@ -1,0 +1,797 @@
+// gfx950 kernels of the state-vector simulator.
+//
+//  k1  plain sweep: one gate over the whole state (Algorithm 1, Section III-A,
+//      with the single-control predicate). Pairs are enumerated by inserting
+//      the fixed bits into a dense counter, so consecutive lanes touch
+//      consecutive amplitudes and every sweep is a coalesced HBM stream.
+//  k2  block-resident pass (the flush of Section III-B): one work-group owns
+//      one block of 2^l amplitudes gathered by address from its l local
+//      memory bits, keeps 2^r of them per thread in registers, applies the
+//      whole deferred gate run and writes the block back.
+//  k3  explicit qubit exchange (the SWAP of Section III-B) as an in-place
+//      pass over the amplitudes whose two bits differ.
+//  k5  FP64 readouts: probabilities, marginals, argmax, norm, and
+//      logical-order gather/scatter.
+//
+// Complex values are interleaved (re, im): float2 for complex64 and double2
+// for complex128. Gate matrices arrive in binary64 and are rounded once.
+// The single-gate arithmetic (cmul, cmad2, hbfly) is shared by k1 and k2 so
+// an unfused partitioned run reproduces the plain run bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "launch.h"
+#include "plan.h"
+
+namespace svk {
+
+template <typename T> struct CT;
+template <> struct CT<float> { using type = float2; };
+template <> struct CT<double> { using type = double2; };
+
+__device__ __forceinline__ float xfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double xfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename C> __host__ __device__ __forceinline__ C mk(double re, double im)
+{
+    C r;
+    r.x = (decltype(r.x))re;
+    r.y = (decltype(r.y))im;
+    return r;
+}
+
+// z * a
+template <typename C> __device__ __forceinline__ C cmul(C z, C a)
+{
+    C r;
+    r.x = xfma(z.x, a.x, -(z.y * a.y));
+    r.y = xfma(z.x, a.y, z.y * a.x);
+    return r;
+}
+
+// u0 * a + u1 * b
+template <typename C> __device__ __forceinline__ C cmad2(C u0, C a, C u1, C b)
+{
+    C r;
+    r.x = xfma(u0.x, a.x, xfma(-u0.y, a.y, xfma(u1.x, b.x, -(u1.y * b.y))));
+    r.y = xfma(u0.x, a.y, xfma(u0.y, a.x, xfma(u1.x, b.y, u1.y * b.x)));
+    return r;
+}
+
+// Hadamard butterfly: ((a+b)/sqrt2, (a-b)/sqrt2)
+template <typename C> __device__ __forceinline__ void hbfly(C &a, C &b)
+{
+    using T = decltype(a.x);
+    const T s = (T)0.70710678118654752440;
+    C x, y;
+    x.x = (a.x + b.x) * s;
+    x.y = (a.y + b.y) * s;
+    y.x = (a.x - b.x) * s;
+    y.y = (a.y - b.y) * s;
+    a = x;
+    b = y;
+}
+
+__device__ __forceinline__ uint64_t insert0(uint64_t x, int b)
+{
+    const uint64_t lo = x & ((1ull << b) - 1ull);
+    return ((x >> b) << (b + 1)) | lo;
+}
+
+// ---------------------------------------------------------------- init
+
+template <typename C> __global__ void __launch_bounds__(256) init_kernel(C *S, uint64_t N)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        C z;
+        z.x = (i == 0) ? 1 : 0;
+        z.y = 0;
+        S[i] = z;
+    }
+}
+
+static unsigned grid_for(uint64_t work, unsigned block, unsigned cap)
+{
+    uint64_t g = (work + block - 1) / block;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+hipError_t init_zero_state(void *S, int n, int dtype, hipStream_t st)
+{
+    const uint64_t N = 1ull << n;
+    const unsigned g = grid_for(N, 256, 8192);
+    if (dtype == 0) init_kernel<float2><<<g, 256, 0, st>>>((float2 *)S, N);
+    else init_kernel<double2><<<g, 256, 0, st>>>((double2 *)S, N);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- k1
+
+constexpr int K1_BLOCK = 256;
+constexpr int K1_PER = 4;
+
+enum { K1_DENSE = 0, K1_H = 1, K1_X = 2 };
+
+// Pairs (j, j + 2^t) with bit t of j clear and, if c >= 0, bit c set.
+template <typename C>
+__global__ void __launch_bounds__(K1_BLOCK)
+k1_pair_kernel(C *__restrict__ S, uint64_t npairs, int t, int c, int kind, C u00, C u01, C u10, C u11)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (K1_BLOCK * K1_PER) + threadIdx.x;
+    const int lo = (c >= 0 && c < t) ? c : t;
+    const int hi = (c >= 0 && c > t) ? c : t;
+    const uint64_t cbit = c >= 0 ? (1ull << c) : 0ull;
+    const uint64_t h = 1ull << t;
+#pragma unroll
+    for (int i = 0; i < K1_PER; ++i) {
+        const uint64_t p = base + (uint64_t)i * K1_BLOCK;
+        if (p >= npairs) break;
+        uint64_t j = insert0(p, lo);
+        if (c >= 0) j = insert0(j, hi);
+        j |= cbit;
+        C a = S[j], b = S[j + h];
+        if (kind == K1_H) {
+            hbfly(a, b);
+            S[j] = a;
+            S[j + h] = b;
+        } else if (kind == K1_X) {
+            S[j] = b;
+            S[j + h] = a;
+        } else {
+            S[j] = cmad2(u00, a, u01, b);
+            S[j + h] = cmad2(u10, a, u11, b);
+        }
+    }
+}
+
+// Diagonal gates. Amplitudes with every bit of `ones` (at most two bits, lo
+// <= hi) set are multiplied by d1 when tsel < 0, else by d0 or d1 according
+// to bit tsel.
+template <typename C>
+__global__ void __launch_bounds__(K1_BLOCK)
+k1_diag_kernel(C *__restrict__ S, uint64_t namps, int nones, int lo, int hi, int tsel, C d0, C d1)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (K1_BLOCK * K1_PER) + threadIdx.x;
+    uint64_t ones = 0;
+    if (nones >= 1) ones |= 1ull << lo;
+    if (nones >= 2) ones |= 1ull << hi;
+#pragma unroll
+    for (int i = 0; i < K1_PER; ++i) {
+        const uint64_t p = base + (uint64_t)i * K1_BLOCK;
+        if (p >= namps) break;
+        uint64_t j = p;
+        if (nones >= 1) j = insert0(j, lo);
+        if (nones >= 2) j = insert0(j, hi);
+        j |= ones;
+        C a = S[j];
+        C d = d1;
+        if (tsel >= 0 && !((j >> tsel) & 1ull)) d = d0;
+        S[j] = cmul(d, a);
+    }
+}
+
+template <typename T> static hipError_t k1_launch(void *Sv, int n, const svp::MGate &g, hipStream_t st)
+{
+    using C = typename CT<T>::type;
+    C *S = (C *)Sv;
+    const double *u = g.u;
+    if (g.cls == svp::GC_DIAG) {
+        const bool ptype = (u[0] == 1.0 && u[1] == 0.0);
+        int bits[2], nb = 0;
+        if (g.c >= 0) bits[nb++] = g.c;
+        if (ptype) bits[nb++] = g.t;
+        if (nb == 2 && bits[0] > bits[1]) { int x = bits[0]; bits[0] = bits[1]; bits[1] = x; }
+        const uint64_t namps = 1ull << (n - nb);
+        const unsigned grid = (unsigned)((namps + K1_BLOCK * K1_PER - 1) / (K1_BLOCK * K1_PER));
+        k1_diag_kernel<C><<<grid, K1_BLOCK, 0, st>>>(S, namps, nb, nb > 0 ? bits[0] : 0,
+                                                     nb > 1 ? bits[1] : 0, ptype ? -1 : g.t,
+                                                     mk<C>(u[0], u[1]), mk<C>(u[6], u[7]));
+        return hipGetLastError();
+    }
+    const uint64_t npairs = 1ull << (n - 1 - (g.c >= 0 ? 1 : 0));
+    const unsigned grid = (unsigned)((npairs + K1_BLOCK * K1_PER - 1) / (K1_BLOCK * K1_PER));
+    const int kind = g.op == 0 ? K1_H : (g.cls == svp::GC_PERM ? K1_X : K1_DENSE);
+    k1_pair_kernel<C><<<grid, K1_BLOCK, 0, st>>>(S, npairs, g.t, g.c, kind, mk<C>(u[0], u[1]),
+                                                 mk<C>(u[2], u[3]), mk<C>(u[4], u[5]),
+                                                 mk<C>(u[6], u[7]));
+    return hipGetLastError();
+}
+
+hipError_t k1_gate(void *S, int n, int dtype, const svp::MGate &g, hipStream_t st)
+{
+    return dtype == 0 ? k1_launch<float>(S, n, g, st) : k1_launch<double>(S, n, g, st);
+}
+
+// ---------------------------------------------------------------- k3
+
+// Exchange memory bits p and v: amplitude i with bit p = 1, bit v = 0 trades
+// places with i ^ 2^p ^ 2^v. Pure data movement, exact.
+template <typename C>
+__global__ void __launch_bounds__(K1_BLOCK) k3_kernel(C *__restrict__ S, uint64_t npairs, int p, int v)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (K1_BLOCK * K1_PER) + threadIdx.x;
+    const int lo = p < v ? p : v, hi = p < v ? v : p;
+    const uint64_t flip = (1ull << p) | (1ull << v);
+#pragma unroll
+    for (int i = 0; i < K1_PER; ++i) {
+        const uint64_t q = base + (uint64_t)i * K1_BLOCK;
+        if (q >= npairs) break;
+        uint64_t j = insert0(insert0(q, lo), hi) | (1ull << p);
+        const uint64_t k = j ^ flip;
+        C a = S[j], b = S[k];
+        S[j] = b;
+        S[k] = a;
+    }
+}
+
+hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st)
+{
+    const uint64_t npairs = 1ull << (n - 2);
+    const unsigned grid = (unsigned)((npairs + K1_BLOCK * K1_PER - 1) / (K1_BLOCK * K1_PER));
+    if (dtype == 0) k3_kernel<float2><<<grid, K1_BLOCK, 0, st>>>((float2 *)S, npairs, p, v);
+    else k3_kernel<double2><<<grid, K1_BLOCK, 0, st>>>((double2 *)S, npairs, p, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- k2
+
+// LDS index swizzle: the low bits that span one 128-byte bank row are XORed
+// with a fold of the higher bits, so lanes whose local indices differ only in
+// high bits still spread over the banks. A bijection on [0, 2^l).
+template <typename C> __device__ __forceinline__ uint32_t swz(uint32_t x)
+{
+    constexpr int E = (sizeof(C) == 8) ? 4 : 3;  // log2(elements per 128 B)
+    constexpr uint32_t M = (1u << E) - 1u;
+    const uint32_t h = x >> E;
+    return x ^ ((h ^ (h >> E) ^ (h >> (2 * E))) & M);
+}
+
+template <int J, int R, typename C>
+__device__ __forceinline__ void k2_pairs(C *a, int kind, const double *v, bool tpred, int ckind, int cslot)
+{
+    const C u00 = mk<C>(v[0], v[1]), u01 = mk<C>(v[2], v[3]);
+    const C u10 = mk<C>(v[4], v[5]), u11 = mk<C>(v[6], v[7]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (k & (1 << J)) continue;
+        if (ckind == svp::CK_SLOT && !((k >> cslot) & 1)) continue;
+        constexpr int H = 1 << J;
+        C x = a[k], y = a[k + H], nx, ny;
+        if (kind == svp::K2_H) {
+            nx = x;
+            ny = y;
+            hbfly(nx, ny);
+        } else if (kind == svp::K2_X) {
+            nx = y;
+            ny = x;
+        } else {
+            nx = cmad2(u00, x, u01, y);
+            ny = cmad2(u10, x, u11, y);
+        }
+        a[k] = tpred ? nx : x;
+        a[k + H] = tpred ? ny : y;
+    }
+}
+
+template <typename T, int LOGR>
+__global__ void __launch_bounds__(1024)
+k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, K2Args args)
+{
+    using C = typename CT<T>::type;
+    constexpr int R = 1 << LOGR;
+    extern __shared__ unsigned char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
+    const int l = args.l;
+    const int tb = l - LOGR;
+    const uint32_t tid = threadIdx.x;
+
+    uint64_t base = 0;
+    {
+        const uint64_t bid = blockIdx.x;
+        for (int i = 0; i < args.n - l; ++i) base |= ((bid >> i) & 1ull) << args.nbits[i];
+    }
+    int rb[LOGR];
+#pragma unroll
+    for (int j = 0; j < LOGR; ++j) rb[j] = tb + j;
+    uint32_t tloc = tid;
+    uint64_t tmem = base;
+    for (int i = 0; i < tb; ++i) tmem |= (uint64_t)((tid >> i) & 1u) << args.bits[i];
+
+    C a[R];
+    {
+        uint64_t roff[LOGR];
+#pragma unroll
+        for (int j = 0; j < LOGR; ++j) roff[j] = 1ull << args.bits[rb[j]];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint64_t addr = tmem;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            a[k] = S[addr];
+        }
+    }
+
+    for (int oi = 0; oi < args.nops; ++oi) {
+        const svp::K2Op &op = ops[oi];
+        const int kind = op.kind;
+        if (kind == svp::K2_LAYOUT) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                uint32_t x = tloc;
+#pragma unroll
+                for (int j = 0; j < LOGR; ++j)
+                    if ((k >> j) & 1) x |= 1u << rb[j];
+                lds[swz<C>(x)] = a[k];
+            }
+            __syncthreads();
+            uint32_t rmask = 0;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j) {
+                rb[j] = (op.a >> (5 * j)) & 31;
+                rmask |= 1u << rb[j];
+            }
+            tloc = 0;
+            tmem = base;
+            int cnt = 0;
+            for (int i = 0; i < l; ++i) {
+                if ((rmask >> i) & 1u) continue;
+                const uint32_t bit = (tid >> cnt) & 1u;
+                tloc |= bit << i;
+                tmem |= (uint64_t)bit << args.bits[i];
+                ++cnt;
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                uint32_t x = tloc;
+#pragma unroll
+                for (int j = 0; j < LOGR; ++j)
+                    if ((k >> j) & 1) x |= 1u << rb[j];
+                a[k] = lds[swz<C>(x)];
+            }
+            __syncthreads();
+        } else if (kind == svp::K2_PHASE) {
+            const bool tpred = (tmem & op.m0) == op.m0;
+            const C z = mk<C>(op.v[0], op.v[1]);
+            const int rmask = op.a;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if ((k & rmask) != rmask) continue;
+                const C y = cmul(z, a[k]);
+                a[k] = tpred ? y : a[k];
+            }
+        } else if (kind == svp::K2_DIAG) {
+            const bool tpred = (tmem & op.m0) == op.m0;
+            const C d0 = mk<C>(op.v[0], op.v[1]), d1 = mk<C>(op.v[2], op.v[3]);
+            const int slot = op.a, rmask = op.c;
+            if (slot >= 0) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if ((k & rmask) != rmask) continue;
+                    const C d = ((k >> slot) & 1) ? d1 : d0;
+                    const C y = cmul(d, a[k]);
+                    a[k] = tpred ? y : a[k];
+                }
+            } else {
+                const bool sel = (tmem >> op.b) & 1ull;
+                C d;
+                d.x = sel ? d1.x : d0.x;
+                d.y = sel ? d1.y : d0.y;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if ((k & rmask) != rmask) continue;
+                    const C y = cmul(d, a[k]);
+                    a[k] = tpred ? y : a[k];
+                }
+            }
+        } else {
+            const int ckind = op.b;
+            const bool tpred = (ckind == svp::CK_MEM) ? (bool)((tmem >> op.c) & 1ull) : true;
+            const int cslot = op.c;
+            switch (op.a) {
+            case 0: k2_pairs<0, R>(a, kind, op.v, tpred, ckind, cslot); break;
+            case 1: if constexpr (LOGR > 1) k2_pairs<1, R>(a, kind, op.v, tpred, ckind, cslot); break;
+            case 2: if constexpr (LOGR > 2) k2_pairs<2, R>(a, kind, op.v, tpred, ckind, cslot); break;
+            case 3: if constexpr (LOGR > 3) k2_pairs<3, R>(a, kind, op.v, tpred, ckind, cslot); break;
+            case 4: if constexpr (LOGR > 4) k2_pairs<4, R>(a, kind, op.v, tpred, ckind, cslot); break;
+            default: break;
+            }
+        }
+    }
+
+    {
+        // the program ends in the canonical layout: registers = top local bits
+        uint64_t roff[LOGR];
+#pragma unroll
+        for (int j = 0; j < LOGR; ++j) roff[j] = 1ull << args.bits[rb[j]];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint64_t addr = tmem;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            S[addr] = a[k];
+        }
+    }
+}
+
+template <typename T, int LOGR>
+static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hipStream_t st)
+{
+    using C = typename CT<T>::type;
+    const size_t lds = (size_t)sizeof(C) << a.l;
+    static size_t attr_bytes = 64 * 1024;
+    if (lds > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)k2_kernel<T, LOGR>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_bytes = lds;
+    }
+    const unsigned threads = 1u << (a.l - LOGR);
+    const uint64_t blocks = 1ull << (a.n - a.l);
+    if (threads > 1024 || blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+    k2_kernel<T, LOGR><<<(unsigned)blocks, threads, lds, st>>>((C *)S, ops, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t k2_dispatch(void *S, int logr, const K2Args &a, const svp::K2Op *ops, hipStream_t st)
+{
+    switch (logr) {
+    case 1: return k2_launch_t<T, 1>(S, a, ops, st);
+    case 2: return k2_launch_t<T, 2>(S, a, ops, st);
+    case 3: return k2_launch_t<T, 3>(S, a, ops, st);
+    case 4: return k2_launch_t<T, 4>(S, a, ops, st);
+    case 5: return k2_launch_t<T, 5>(S, a, ops, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *ops,
+                   hipStream_t st)
+{
+    if (a.l < logr || a.l > n) return hipErrorInvalidValue;
+    return dtype == 0 ? k2_dispatch<float>(S, logr, a, ops, st)
+                      : k2_dispatch<double>(S, logr, a, ops, st);
+}
+
+// ---------------------------------------------------------------- k5 readouts
+
+struct PermArg {
+    int8_t p[48];
+    int n;
+    int ident;
+};
+
+static PermArg make_perm(const int *perm, int n)
+{
+    PermArg pa{};
+    pa.n = n;
+    pa.ident = 1;
+    for (int q = 0; q < n; ++q) {
+        pa.p[q] = (int8_t)(perm ? perm[q] : q);
+        if (pa.p[q] != q) pa.ident = 0;
+    }
+    return pa;
+}
+
+__device__ __forceinline__ uint64_t phys_of(uint64_t x, const PermArg &pa)
+{
+    if (pa.ident) return x;
+    uint64_t p = 0;
+    for (int q = 0; q < pa.n; ++q) p |= ((x >> q) & 1ull) << pa.p[q];
+    return p;
+}
+
+template <typename C> __device__ __forceinline__ double prob(C a)
+{
+    const double re = (double)a.x, im = (double)a.y;
+    return re * re + im * im;
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256)
+probs_kernel(const C *__restrict__ S, PermArg pa, double *__restrict__ out, uint64_t off, uint64_t cnt)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+        out[i] = prob(S[phys_of(off + i, pa)]);
+}
+
+hipError_t probabilities(const void *S, int n, int dtype, const int *perm, double *out,
+                         uint64_t offset, uint64_t count, hipStream_t st)
+{
+    const PermArg pa = make_perm(perm, n);
+    const unsigned g = grid_for(count, 256, 16384);
+    if (dtype == 0) probs_kernel<float2><<<g, 256, 0, st>>>((const float2 *)S, pa, out, offset, count);
+    else probs_kernel<double2><<<g, 256, 0, st>>>((const double2 *)S, pa, out, offset, count);
+    return hipGetLastError();
+}
+
+struct BitList {
+    int8_t b[48];
+    int cnt;
+};
+
+__device__ __forceinline__ uint64_t deposit(uint64_t v, const BitList &bl)
+{
+    uint64_t r = 0;
+    for (int k = 0; k < bl.cnt; ++k) r |= ((v >> k) & 1ull) << bl.b[k];
+    return r;
+}
+
+// Each thread owns one marginal entry m and sums its 2^(n-nq) terms in order.
+template <typename C>
+__global__ void __launch_bounds__(256)
+marg_direct_kernel(const C *__restrict__ S, BitList qb, BitList ob, double *__restrict__ out)
+{
+    const uint64_t M = 1ull << qb.cnt, O = 1ull << ob.cnt;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += stride) {
+        const uint64_t bm = deposit(m, qb);
+        double s = 0.0;
+        for (uint64_t o = 0; o < O; ++o) s += prob(S[bm | deposit(o, ob)]);
+        out[m] = s;
+    }
+}
+
+// Small marginals: work-group (m, g) reduces chunk g of m's terms; the
+// partials are then summed in fixed order. Deterministic.
+constexpr int MARG_G = 256;
+
+template <typename C>
+__global__ void __launch_bounds__(256)
+marg_chunk_kernel(const C *__restrict__ S, BitList qb, BitList ob, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const uint64_t m = blockIdx.y;
+    const uint64_t O = 1ull << ob.cnt;
+    const uint64_t per = (O + MARG_G - 1) / MARG_G;
+    const uint64_t o0 = (uint64_t)blockIdx.x * per;
+    uint64_t o1 = o0 + per;
+    if (o1 > O) o1 = O;
+    const uint64_t bm = deposit(m, qb);
+    double s = 0.0;
+    for (uint64_t o = o0 + threadIdx.x; o < o1; o += blockDim.x) s += prob(S[bm | deposit(o, ob)]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[m * MARG_G + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) marg_finish_kernel(const double *__restrict__ part, uint64_t M,
+                                                          double *__restrict__ out)
+{
+    const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    double s = 0.0;
+    for (int g = 0; g < MARG_G; ++g) s += part[m * MARG_G + g];
+    out[m] = s;
+}
+
+static BitList make_bits(const int *b, int cnt)
+{
+    BitList bl{};
+    bl.cnt = cnt;
+    for (int k = 0; k < cnt; ++k) bl.b[k] = (int8_t)b[k];
+    return bl;
+}
+
+size_t marginal_scratch_bytes(int n, int nq)
+{
+    if (n - nq <= 12) return 0;
+    return (size_t)sizeof(double) * MARG_G << nq;
+}
+
+template <typename C>
+static hipError_t marginal_t(const C *S, int n, const int *qbits, int nq, const int *obits,
+                             double *out, void *scratch, hipStream_t st)
+{
+    const BitList qb = make_bits(qbits, nq), ob = make_bits(obits, n - nq);
+    const uint64_t M = 1ull << nq;
+    if (n - nq <= 12) {
+        marg_direct_kernel<C><<<grid_for(M, 256, 65535), 256, 0, st>>>(S, qb, ob, out);
+        return hipGetLastError();
+    }
+    if (M > 65535) return hipErrorInvalidValue;
+    double *part = (double *)scratch;
+    dim3 grid(MARG_G, (unsigned)M);
+    marg_chunk_kernel<C><<<grid, 256, 0, st>>>(S, qb, ob, part);
+    marg_finish_kernel<<<grid_for(M, 256, 65535), 256, 0, st>>>(part, M, out);
+    return hipGetLastError();
+}
+
+hipError_t marginal(const void *S, int n, int dtype, const int *qbits, int nq, const int *obits,
+                    double *out, void *scratch, hipStream_t st)
+{
+    return dtype == 0 ? marginal_t((const float2 *)S, n, qbits, nq, obits, out, scratch, st)
+                      : marginal_t((const double2 *)S, n, qbits, nq, obits, out, scratch, st);
+}
+
+// argmax with the lowest index winning ties
+__device__ __forceinline__ bool better(double v1, uint64_t i1, double v2, uint64_t i2)
+{
+    return v1 > v2 || (v1 == v2 && i1 < i2);
+}
+
+constexpr int AM_BLOCKS = 1024;
+
+__device__ void block_argmax(double v, uint64_t i, double *rv, uint64_t *ri, double *outv, uint64_t *outi)
+{
+    __shared__ double sv[256];
+    __shared__ uint64_t si[256];
+    sv[threadIdx.x] = v;
+    si[threadIdx.x] = i;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double v2 = sv[threadIdx.x + w];
+            const uint64_t i2 = si[threadIdx.x + w];
+            if (better(v2, i2, sv[threadIdx.x], si[threadIdx.x])) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *outv = sv[0];
+        *outi = si[0];
+    }
+    (void)rv;
+    (void)ri;
+}
+
+__global__ void __launch_bounds__(256) argmax_stage1(const double *__restrict__ p, uint64_t len,
+                                                     double *pv, uint64_t *pi)
+{
+    double bv = -1.0;
+    uint64_t bi = ~0ull;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+        if (better(p[i], i, bv, bi)) { bv = p[i]; bi = i; }
+    block_argmax(bv, bi, nullptr, nullptr, &pv[blockIdx.x], &pi[blockIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) argmax_stage2(const double *pv, const uint64_t *pi, int nparts,
+                                                     uint64_t *res_idx, double *res_val)
+{
+    double bv = -1.0;
+    uint64_t bi = ~0ull;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x)
+        if (better(pv[i], pi[i], bv, bi)) { bv = pv[i]; bi = pi[i]; }
+    block_argmax(bv, bi, nullptr, nullptr, res_val, res_idx);
+}
+
+size_t argmax_scratch_bytes(uint64_t) { return (size_t)AM_BLOCKS * (sizeof(double) + sizeof(uint64_t)); }
+
+hipError_t argmax(const double *p, uint64_t len, void *scratch, uint64_t *res_idx, double *res_val,
+                  hipStream_t st)
+{
+    double *pv = (double *)scratch;
+    uint64_t *pi = (uint64_t *)(pv + AM_BLOCKS);
+    const unsigned g = grid_for(len, 256, AM_BLOCKS);
+    argmax_stage1<<<g, 256, 0, st>>>(p, len, pv, pi);
+    argmax_stage2<<<1, 256, 0, st>>>(pv, pi, (int)g, res_idx, res_val);
+    return hipGetLastError();
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) marg_argmax_stage1(const C *__restrict__ S, BitList qb, BitList ob,
+                                                          double *pv, uint64_t *pi)
+{
+    const uint64_t M = 1ull << qb.cnt, O = 1ull << ob.cnt;
+    double bv = -1.0;
+    uint64_t bi = ~0ull;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += stride) {
+        const uint64_t bm = deposit(m, qb);
+        double s = 0.0;
+        for (uint64_t o = 0; o < O; ++o) s += prob(S[bm | deposit(o, ob)]);
+        if (better(s, m, bv, bi)) { bv = s; bi = m; }
+    }
+    block_argmax(bv, bi, nullptr, nullptr, &pv[blockIdx.x], &pi[blockIdx.x]);
+}
+
+hipError_t marginal_argmax(const void *S, int n, int dtype, const int *qbits, int nq, const int *obits,
+                           void *scratch, uint64_t *res_idx, double *res_val, hipStream_t st)
+{
+    const BitList qb = make_bits(qbits, nq), ob = make_bits(obits, n - nq);
+    double *pv = (double *)scratch;
+    uint64_t *pi = (uint64_t *)(pv + AM_BLOCKS);
+    const unsigned g = grid_for(1ull << nq, 256, AM_BLOCKS);
+    if (dtype == 0) marg_argmax_stage1<float2><<<g, 256, 0, st>>>((const float2 *)S, qb, ob, pv, pi);
+    else marg_argmax_stage1<double2><<<g, 256, 0, st>>>((const double2 *)S, qb, ob, pv, pi);
+    argmax_stage2<<<1, 256, 0, st>>>(pv, pi, (int)g, res_idx, res_val);
+    return hipGetLastError();
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) norm_stage1(const C *__restrict__ S, uint64_t N, double *part)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) s += prob(S[i]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) norm_stage2(const double *part, int nparts, double *res)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *res = red[0];
+}
+
+size_t norm_scratch_bytes(int) { return (size_t)AM_BLOCKS * sizeof(double); }
+
+hipError_t norm2(const void *S, int n, int dtype, void *scratch, double *res, hipStream_t st)
+{
+    const uint64_t N = 1ull << n;
+    const unsigned g = grid_for(N, 256, AM_BLOCKS);
+    double *part = (double *)scratch;
+    if (dtype == 0) norm_stage1<float2><<<g, 256, 0, st>>>((const float2 *)S, N, part);
+    else norm_stage1<double2><<<g, 256, 0, st>>>((const double2 *)S, N, part);
+    norm_stage2<<<1, 256, 0, st>>>(part, (int)g, res);
+    return hipGetLastError();
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) gather_kernel(const C *__restrict__ S, PermArg pa, C *__restrict__ out,
+                                                     uint64_t off, uint64_t cnt)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+        out[i] = S[phys_of(off + i, pa)];
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) scatter_kernel(C *__restrict__ S, PermArg pa, const C *__restrict__ in,
+                                                      uint64_t off, uint64_t cnt)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+        S[phys_of(off + i, pa)] = in[i];
+}
+
+hipError_t gather_logical(const void *S, int n, int dtype, const int *perm, void *out, uint64_t offset,
+                          uint64_t count, hipStream_t st)
+{
+    const PermArg pa = make_perm(perm, n);
+    const unsigned g = grid_for(count, 256, 16384);
+    if (dtype == 0) gather_kernel<float2><<<g, 256, 0, st>>>((const float2 *)S, pa, (float2 *)out, offset, count);
+    else gather_kernel<double2><<<g, 256, 0, st>>>((const double2 *)S, pa, (double2 *)out, offset, count);
+    return hipGetLastError();
+}
+
+hipError_t scatter_logical(void *S, int n, int dtype, const int *perm, const void *in, uint64_t offset,
+                           uint64_t count, hipStream_t st)
+{
+    const PermArg pa = make_perm(perm, n);
+    const unsigned g = grid_for(count, 256, 16384);
+    if (dtype == 0) scatter_kernel<float2><<<g, 256, 0, st>>>((float2 *)S, pa, (const float2 *)in, offset, count);
+    else scatter_kernel<double2><<<g, 256, 0, st>>>((double2 *)S, pa, (const double2 *)in, offset, count);
+    return hipGetLastError();
+}
+
+}  // namespace svk

@@ -1,0 +1,58 @@
+// Host-side launchers of the gfx950 kernels (defined in kernels.hip).
+// Every launcher enqueues on `stream` and returns the hipError_t of the
+// launch (hipSuccess on success).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace svk {
+
+// Block-pass arguments passed by value.
+struct K2Args {
+    int n;
+    int l;
+    int nops;
+    int pad;
+    int8_t bits[48];    // memory bit of each local bit, ascending
+    int8_t nbits[48];   // memory bits outside the block, ascending
+};
+
+hipError_t init_zero_state(void *S, int n, int dtype, hipStream_t st);
+hipError_t k1_gate(void *S, int n, int dtype, const svp::MGate &g, hipStream_t st);
+hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st);
+hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *dev_ops,
+                   hipStream_t st);
+
+// Readouts (FP64). perm: HOST array of n ints, perm[q] = physical bit of
+// logical bit q, or nullptr for the identity (passed to the kernel by value).
+hipError_t probabilities(const void *S, int n, int dtype, const int *perm, double *out,
+                         uint64_t offset, uint64_t count, hipStream_t st);
+// Marginal over `nq` qubits given as physical bit positions (HOST array
+// `qbits`, nq entries) and the complementary physical bits (`obits`, n-nq
+// entries, ascending). out: 2^nq doubles on the device. scratch: at least
+// marginal_scratch_bytes(n, nq) bytes of device memory.
+size_t marginal_scratch_bytes(int n, int nq);
+hipError_t marginal(const void *S, int n, int dtype, const int *qbits, int nq, const int *obits,
+                    double *out, void *scratch, hipStream_t st);
+// Argmax of a device FP64 array; lowest index wins ties. Result written to
+// res[0] (index as double-punned uint64) and val[0]. scratch: argmax_scratch_bytes.
+size_t argmax_scratch_bytes(uint64_t len);
+hipError_t argmax(const double *p, uint64_t len, void *scratch, uint64_t *res_idx, double *res_val,
+                  hipStream_t st);
+// Fused marginal + argmax for marginals whose complement is small.
+hipError_t marginal_argmax(const void *S, int n, int dtype, const int *qbits, int nq,
+                           const int *obits, void *scratch, uint64_t *res_idx, double *res_val,
+                           hipStream_t st);
+size_t norm_scratch_bytes(int n);
+hipError_t norm2(const void *S, int n, int dtype, void *scratch, double *res, hipStream_t st);
+// Logical-order gather: out[i] = S[phys(offset + i)] for i < count.
+hipError_t gather_logical(const void *S, int n, int dtype, const int *perm, void *out,
+                          uint64_t offset, uint64_t count, hipStream_t st);
+hipError_t scatter_logical(void *S, int n, int dtype, const int *perm, const void *in,
+                           uint64_t offset, uint64_t count, hipStream_t st);
+
+}  // namespace svk

@@ -1,0 +1,401 @@
+// Host planner: gate list -> device steps. See plan.h for the model.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace svp {
+
+namespace {
+enum { OP_H = 0, OP_X, OP_Y, OP_Z, OP_RX, OP_RY, OP_RZ, OP_P, OP_U2, OP_SWAP };
+
+int amp_bytes(int dtype) { return dtype == 0 ? 8 : 16; }
+// Low memory bits spanning one 128-byte segment.
+int segment_bits(int dtype) { return dtype == 0 ? 4 : 3; }
+}  // namespace
+
+int default_block_qubits(int dtype) { return dtype == 0 ? 13 : 12; }
+int max_block_qubits(int dtype) { return dtype == 0 ? 14 : 13; }
+
+bool gate_matrix(int op, double theta, const double *u_in, double *u, int *cls)
+{
+    const double s = 0.70710678118654752440;  // 1/sqrt(2)
+    const double ch = std::cos(0.5 * theta), sh = std::sin(0.5 * theta);
+    std::memset(u, 0, 8 * sizeof(double));
+    int k = GC_DENSE;
+    switch (op) {
+    case OP_H: u[0] = s; u[2] = s; u[4] = s; u[6] = -s; break;
+    case OP_X: u[2] = 1.0; u[4] = 1.0; k = GC_PERM; break;
+    case OP_Y: u[3] = -1.0; u[5] = 1.0; break;
+    case OP_Z: u[0] = 1.0; u[6] = -1.0; k = GC_DIAG; break;
+    case OP_RX: u[0] = ch; u[3] = -sh; u[5] = -sh; u[6] = ch; break;
+    case OP_RY: u[0] = ch; u[2] = -sh; u[4] = sh; u[6] = ch; break;
+    case OP_RZ: u[0] = ch; u[1] = -sh; u[6] = ch; u[7] = sh; k = GC_DIAG; break;
+    case OP_P: u[0] = 1.0; u[6] = std::cos(theta); u[7] = std::sin(theta); k = GC_DIAG; break;
+    case OP_U2:
+        std::memcpy(u, u_in, 8 * sizeof(double));
+        if (u[2] == 0.0 && u[3] == 0.0 && u[4] == 0.0 && u[5] == 0.0) k = GC_DIAG;
+        break;
+    default: return false;
+    }
+    *cls = k;
+    return true;
+}
+
+std::string validate(int n, const RawGate *g, size_t m)
+{
+    if (m > 0 && !g) return "gate array is null";
+    for (size_t i = 0; i < m; ++i) {
+        const RawGate &x = g[i];
+        const std::string at = " (gate " + std::to_string(i) + ")";
+        if (x.op < OP_H || x.op > OP_SWAP) return "unknown op" + at;
+        if (x.target < 0 || x.target >= n) return "target out of range" + at;
+        if (x.op == OP_SWAP) {
+            if (x.target2 < 0 || x.target2 >= n || x.target2 == x.target)
+                return "SWAP needs two distinct qubits" + at;
+            if (x.control >= 0) return "SWAP takes no control" + at;
+            continue;
+        }
+        if (x.control < -1 || x.control >= n) return "control out of range" + at;
+        if (x.control == x.target) return "control equals target" + at;
+        if (!std::isfinite(x.theta)) return "non-finite angle" + at;
+        if (x.op == OP_U2)
+            for (int k = 0; k < 8; ++k)
+                if (!std::isfinite(x.u[k])) return "non-finite matrix entry" + at;
+    }
+    return "";
+}
+
+namespace {
+
+struct Builder {
+    const PlanConfig &cfg;
+    Plan &plan;
+    int n, l, logr, ab, sbits;
+    double state_bytes;
+
+    Builder(const PlanConfig &c, Plan &p) : cfg(c), plan(p)
+    {
+        n = c.n;
+        ab = amp_bytes(c.dtype);
+        sbits = segment_bits(c.dtype);
+        state_bytes = std::ldexp((double)ab, n);
+        l = 0;
+        logr = 0;
+    }
+
+    // Algorithmic bytes of one plain sweep: a condition bit at or above the
+    // segment size halves the segments touched.
+    double k1_bytes(const MGate &g) const
+    {
+        double b = 2.0 * state_bytes;
+        if (g.c >= sbits) b *= 0.5;
+        if (g.cls == GC_DIAG && g.u[0] == 1.0 && g.u[1] == 0.0 && g.t >= sbits) b *= 0.5;
+        return b;
+    }
+
+    void add_k1(const MGate &g)
+    {
+        Step s;
+        s.kind = ST_K1;
+        s.g = g;
+        s.ngates = 1;
+        plan.steps.push_back(s);
+        plan.stats.passes += 1;
+        plan.stats.bytes += k1_bytes(g);
+    }
+
+    // ---- block-pass compilation ---------------------------------------
+    void compile_block(const std::vector<MGate> &q, const std::vector<int> &B)
+    {
+        const int r = logr;
+        std::vector<int> rank(64, -1);
+        for (int i = 0; i < (int)B.size(); ++i) rank[B[i]] = i;
+        std::vector<int> canon(r);
+        for (int j = 0; j < r; ++j) canon[j] = l - r + j;
+        std::vector<int> rb = canon;  // register slot j holds local bit rb[j]
+        auto slot_of = [&](int local) {
+            for (int j = 0; j < r; ++j)
+                if (rb[j] == local) return j;
+            return -1;
+        };
+        auto emit_layout = [&](std::vector<int> nrb) {
+            std::sort(nrb.begin(), nrb.end());
+            if (nrb == rb) return;
+            K2Op op{};
+            op.kind = K2_LAYOUT;
+            int packed = 0;
+            for (int j = 0; j < r; ++j) packed |= nrb[j] << (5 * j);
+            op.a = packed;
+            plan.ops.push_back(op);
+            rb = nrb;
+        };
+        const int begin = (int)plan.ops.size();
+        for (size_t i = 0; i < q.size(); ++i) {
+            const MGate &g = q[i];
+            if (g.cls == GC_DIAG) {
+                K2Op op{};
+                const bool ptype = (g.u[0] == 1.0 && g.u[1] == 0.0);
+                int rmask = 0;
+                uint64_t tmask = 0;
+                auto cond = [&](int p) {
+                    const int lb = rank[p];
+                    const int sl = lb >= 0 ? slot_of(lb) : -1;
+                    if (sl >= 0) rmask |= 1 << sl;
+                    else tmask |= 1ull << p;
+                };
+                if (g.c >= 0) cond(g.c);
+                if (ptype) {
+                    cond(g.t);
+                    op.kind = K2_PHASE;
+                    op.a = rmask;
+                    op.m0 = tmask;
+                    op.v[0] = g.u[6];
+                    op.v[1] = g.u[7];
+                } else {
+                    const int lb = rank[g.t];
+                    const int sl = lb >= 0 ? slot_of(lb) : -1;
+                    op.kind = K2_DIAG;
+                    op.a = sl;
+                    op.b = g.t;
+                    op.c = rmask;
+                    op.m0 = tmask;
+                    op.v[0] = g.u[0]; op.v[1] = g.u[1];
+                    op.v[2] = g.u[6]; op.v[3] = g.u[7];
+                }
+                plan.ops.push_back(op);
+                continue;
+            }
+            const int lt = rank[g.t];
+            if (slot_of(lt) < 0) {
+                // new register set: this target, then the next distinct
+                // non-diagonal targets of the run, then current slots
+                std::vector<int> nrb{lt};
+                for (size_t k = i + 1; k < q.size() && (int)nrb.size() < r; ++k) {
+                    if (q[k].cls == GC_DIAG) continue;
+                    const int x = rank[q[k].t];
+                    if (std::find(nrb.begin(), nrb.end(), x) == nrb.end()) nrb.push_back(x);
+                }
+                for (int j = 0; j < r && (int)nrb.size() < r; ++j)
+                    if (std::find(nrb.begin(), nrb.end(), rb[j]) == nrb.end()) nrb.push_back(rb[j]);
+                for (int x = l - 1; x >= 0 && (int)nrb.size() < r; --x)
+                    if (std::find(nrb.begin(), nrb.end(), x) == nrb.end()) nrb.push_back(x);
+                emit_layout(nrb);
+            }
+            K2Op op{};
+            op.kind = g.op == OP_H ? K2_H : (g.cls == GC_PERM ? K2_X : K2_DENSE);
+            op.a = slot_of(lt);
+            if (g.c < 0) {
+                op.b = CK_NONE;
+            } else {
+                const int lc = rank[g.c];
+                const int sc = lc >= 0 ? slot_of(lc) : -1;
+                if (sc >= 0) { op.b = CK_SLOT; op.c = sc; }
+                else { op.b = CK_MEM; op.c = g.c; }
+            }
+            for (int k = 0; k < 8; ++k) op.v[k] = g.u[k];
+            plan.ops.push_back(op);
+        }
+        emit_layout(canon);
+        Step s;
+        s.kind = ST_K2;
+        s.l = l;
+        s.logr = r;
+        for (int i = 0; i < l; ++i) s.bits[i] = B[i];
+        s.op_begin = begin;
+        s.op_count = (int)plan.ops.size() - begin;
+        s.ngates = (int)q.size();
+        plan.steps.push_back(s);
+        plan.stats.phases += 1;
+        plan.stats.passes += 1;
+        plan.stats.bytes += 2.0 * state_bytes;
+    }
+};
+
+}  // namespace
+
+std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
+                      const std::vector<int> &l2p_in, Plan &plan)
+{
+    plan = Plan();
+    const int n = cfg.n;
+    if (n < 1 || n > 40) return "n out of range";
+    if ((int)l2p_in.size() != n) return "layout size mismatch";
+    std::string err = validate(n, gates, m);
+    if (!err.empty()) return err;
+    Builder b(cfg, plan);
+    std::vector<int> l2p = l2p_in, p2l(n);
+    for (int q = 0; q < n; ++q) p2l[l2p[q]] = q;
+
+    auto to_mgate = [&](const RawGate &x, MGate &g) {
+        g.op = x.op;
+        gate_matrix(x.op, x.theta, x.u, g.u, &g.cls);
+        g.t = l2p[x.target];
+        g.c = x.control >= 0 ? l2p[x.control] : -1;
+    };
+    auto relabel = [&](int a, int bq) {
+        const int pa = l2p[a], pb = l2p[bq];
+        l2p[a] = pb; l2p[bq] = pa;
+        p2l[pb] = a; p2l[pa] = bq;
+    };
+
+    int l = cfg.l > 0 ? cfg.l : default_block_qubits(cfg.dtype);
+    if (l > n) l = n;
+    const bool partitioned = cfg.mode == 1;
+    if (!partitioned) {
+        for (size_t i = 0; i < m; ++i) {
+            if (gates[i].op == 9) { relabel(gates[i].target, gates[i].target2); continue; }
+            MGate g;
+            to_mgate(gates[i], g);
+            b.add_k1(g);
+            plan.stats.gates += 1;
+        }
+        plan.l2p_after = l2p;
+        plan.l = n;
+        return "";
+    }
+    if (l > max_block_qubits(cfg.dtype)) return "block_qubits above the on-chip maximum";
+    b.l = l;
+    b.logr = std::min(cfg.logr, l);
+    plan.l = l;
+    const bool explicit_remap = cfg.remap == 1;
+    int pin = 0;
+    if (!explicit_remap) {
+        pin = cfg.pin_low >= 0 ? cfg.pin_low : b.sbits;
+        pin = std::min(pin, l - 1);
+        if (pin < 0) pin = 0;
+    }
+
+    // slots 0..l-1; slot v holds memory bit slot_mem[v]
+    std::vector<int> slot_mem(l), mem_slot(64, -1);
+    std::vector<int64_t> last_use(l, -1);
+    for (int v = 0; v < l; ++v) { slot_mem[v] = v; mem_slot[v] = v; }
+    std::vector<MGate> queue;
+    std::vector<int> cls(m, 0);
+    for (size_t i = 0; i < m; ++i) {
+        double tmp[8];
+        if (gates[i].op != 9) gate_matrix(gates[i].op, gates[i].theta, gates[i].u, tmp, &cls[i]);
+    }
+    auto needs_local = [&](size_t i) { return !(cfg.diag_free && cls[i] == GC_DIAG); };
+
+    auto flush = [&]() {
+        if (queue.empty()) return;
+        std::vector<int> B(slot_mem.begin(), slot_mem.end());
+        std::sort(B.begin(), B.end());
+        b.compile_block(queue, B);
+        queue.clear();
+    };
+
+    // next time (gate index > i) the data now at memory bit p is the target of
+    // a gate that needs it local; circuit SWAPs rename it on the way
+    auto next_use = [&](size_t i, int p) -> int64_t {
+        int name = p2l[p];
+        for (size_t k = i + 1; k < m; ++k) {
+            const RawGate &x = gates[k];
+            if (x.op == 9) {
+                if (name == x.target) name = x.target2;
+                else if (name == x.target2) name = x.target;
+                continue;
+            }
+            if (x.target == name && needs_local(k)) return (int64_t)k;
+        }
+        return std::numeric_limits<int64_t>::max();
+    };
+
+    // Bulk remap (virtual remap + look-ahead): when a flush is forced, the
+    // next block gathers the pinned bits plus the memory bits that the
+    // upcoming gates target first, so one pass serves as many targets as
+    // fit. No data moves, so replacing many local qubits costs nothing.
+    const bool bulk = !explicit_remap && cfg.policy == 1;
+    auto bulk_remap = [&](size_t i) {
+        std::vector<int> want;
+        std::vector<int> l2p_f = l2p;
+        std::vector<bool> chosen(64, false);
+        for (int p = 0; p < pin; ++p) chosen[p] = true;
+        for (size_t k = i; k < m && (int)want.size() < l - pin; ++k) {
+            const RawGate &y = gates[k];
+            if (y.op == 9) {
+                std::swap(l2p_f[y.target], l2p_f[y.target2]);
+                continue;
+            }
+            if (!needs_local(k)) continue;
+            const int p = l2p_f[y.target];
+            if (!chosen[p]) { chosen[p] = true; want.push_back(p); }
+        }
+        // keep current local bits in the remaining places
+        for (int v = 0; v < l && (int)want.size() < l - pin; ++v)
+            if (!chosen[slot_mem[v]]) { chosen[slot_mem[v]] = true; want.push_back(slot_mem[v]); }
+        std::vector<bool> keep(64, false);
+        for (int p : want) keep[p] = true;
+        for (int p = 0; p < pin; ++p) keep[p] = true;
+        // slots whose bit is not kept receive the new bits, in slot order
+        std::vector<int> incoming;
+        for (int p : want)
+            if (mem_slot[p] < 0) incoming.push_back(p);
+        size_t next = 0;
+        for (int v = 0; v < l && next < incoming.size(); ++v) {
+            if (keep[slot_mem[v]]) continue;
+            mem_slot[slot_mem[v]] = -1;
+            slot_mem[v] = incoming[next++];
+            mem_slot[slot_mem[v]] = v;
+            last_use[v] = (int64_t)i;
+            plan.stats.swaps += 1;
+        }
+    };
+
+    for (size_t i = 0; i < m; ++i) {
+        const RawGate &x = gates[i];
+        if (x.op == 9) { relabel(x.target, x.target2); continue; }
+        MGate g;
+        to_mgate(x, g);
+        if (bulk && needs_local(i) && mem_slot[g.t] < 0) {
+            flush();
+            bulk_remap(i);
+        } else if (needs_local(i) && mem_slot[g.t] < 0) {
+            flush();
+            int victim = -1;
+            int64_t best_key = 0, best_lru = 0;
+            for (int v = 0; v < l; ++v) {
+                if (slot_mem[v] < pin) continue;
+                int64_t key = cfg.policy == 1 ? -next_use(i, slot_mem[v]) : 0;
+                if (victim < 0 || key < best_key || (key == best_key && last_use[v] < best_lru)) {
+                    victim = v;
+                    best_key = key;
+                    best_lru = last_use[v];
+                }
+            }
+            if (victim < 0) return "no local slot can be evicted (block too small)";
+            plan.stats.swaps += 1;
+            if (explicit_remap) {
+                // exchange memory bits g.t and victim (slot v == memory bit v)
+                const int pv = victim, pt = g.t;
+                Step s;
+                s.kind = ST_K3;
+                s.p = pt;
+                s.v = pv;
+                plan.steps.push_back(s);
+                plan.stats.passes += 1;
+                plan.stats.bytes += 2.0 * b.state_bytes * (pv < b.sbits ? 1.0 : 0.5);
+                const int qa = p2l[pt], qb = p2l[pv];
+                l2p[qa] = pv; l2p[qb] = pt;
+                p2l[pv] = qa; p2l[pt] = qb;
+                to_mgate(x, g);
+            } else {
+                mem_slot[slot_mem[victim]] = -1;
+                slot_mem[victim] = g.t;
+                mem_slot[g.t] = victim;
+            }
+            last_use[victim] = (int64_t)i;
+        }
+        queue.push_back(g);
+        plan.stats.gates += 1;
+        if (mem_slot[g.t] >= 0) last_use[mem_slot[g.t]] = (int64_t)i;
+    }
+    flush();
+    plan.l2p_after = l2p;
+    return "";
+}
+
+}  // namespace svp

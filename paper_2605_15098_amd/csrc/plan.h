@@ -1,0 +1,127 @@
+// Host-side planner: turns a gate list into the device work of one
+// sv_apply_circuit call. Pure C++17, no HIP types, so it runs and is tested
+// without a GPU.
+//
+// Two schedules:
+//  - plain: one whole-state sweep per gate (Algorithm 1 of Section III-A);
+//  - partitioned (Section III-B): the state is split into blocks of 2^l
+//    amplitudes; gates whose target is local are deferred and, when a gate
+//    with a global target arrives (or the circuit ends), the deferred run is
+//    applied block by block in one block-resident pass; the global target is
+//    then brought into the block in place of a victim chosen by LRU (the
+//    paper) or by furthest next use, and the logical-to-physical map is
+//    updated. A global control is decided per block.
+//
+// Device program of one block-resident pass: every work-group holds one
+// block, 2^r amplitudes per thread in registers ("register slots"), the
+// other l-r local bits spread over lanes and waves. Gates target register
+// slots; a layout op moves the block through LDS so that other local bits
+// become register slots. Diagonal gates act on any bit.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace svp {
+
+// Gate classes after matrix construction.
+enum GateClass { GC_DENSE = 0, GC_DIAG = 1, GC_PERM = 2 };
+
+// A gate in memory-bit coordinates with its FP64 matrix.
+struct MGate {
+    int cls;        // GateClass
+    int op;         // original op code (SV_H ...)
+    int t;          // memory bit of the target
+    int c;          // memory bit of the control, -1 for none
+    double u[8];    // row-major 2x2 (re, im)
+};
+
+// Block-pass ops (device program). Field meaning per kind is documented at
+// the kernel that executes them.
+enum K2Kind {
+    K2_LAYOUT = 0, // a: packed register local bits (5 bits each)
+    K2_DENSE = 1,  // a: slot; b: control kind; c: control slot or memory bit
+    K2_H = 2,      // as K2_DENSE, fixed matrix
+    K2_X = 3,      // as K2_DENSE, exchange
+    K2_PHASE = 4,  // m0: memory-bit mask; a: slot mask; v[0..1]: factor
+    K2_DIAG = 5,   // a: target slot or -1; b: target memory bit; c: slot mask;
+                   // m0: memory-bit mask; v[0..1]: d0, v[2..3]: d1
+    K2_FUSED = 6,  // a: slot mask of the k fused bits (k = b); m0: control
+                   // memory mask; c: index of the 2^k x 2^k matrix in the
+                   // matrix table
+};
+enum CtlKind { CK_NONE = 0, CK_SLOT = 1, CK_MEM = 2 };
+
+struct K2Op {
+    int32_t kind, a, b, c;
+    uint64_t m0, m1;
+    double v[8];
+};
+static_assert(sizeof(K2Op) == 96, "K2Op layout");
+
+enum StepKind {
+    ST_K1 = 0,  // one plain sweep for one gate
+    ST_K2 = 1,  // one block-resident pass
+    ST_K3 = 2,  // explicit exchange of memory bits p and v
+};
+
+struct Step {
+    int kind = 0;
+    MGate g{};              // ST_K1
+    int l = 0;              // ST_K2: local bits
+    int logr = 0;           // ST_K2: register bits per thread
+    int bits[64] = {0};     // ST_K2: memory bit of each local bit (ascending)
+    int op_begin = 0, op_count = 0;
+    int p = 0, v = 0;       // ST_K3
+    int ngates = 0;         // gates applied by this step
+};
+
+struct PlanConfig {
+    int n = 0;
+    int dtype = 0;            // 0 = complex64, 1 = complex128
+    int mode = 1;             // 0 plain, 1 partitioned
+    int l = 0;                // block qubits (0 = default)
+    int logr = 4;             // register bits per thread
+    int policy = 0;           // 0 LRU, 1 look-ahead
+    int remap = 0;            // 0 virtual, 1 explicit
+    int diag_free = 0;        // diagonal gates never force a SWAP
+    int pin_low = -1;         // low memory bits kept in every block (-1 = auto)
+    int fuse_k = 1;           // fusion width (1 = off)
+};
+
+struct PlanStats {
+    int64_t gates = 0, swaps = 0, phases = 0, passes = 0, fused = 0;
+    double bytes = 0.0;
+};
+
+struct Plan {
+    std::vector<Step> steps;
+    std::vector<K2Op> ops;
+    std::vector<double> fused_mats;  // 2^k x 2^k complex, row-major (re, im)
+    PlanStats stats;
+    std::vector<int> l2p_after;      // layout after the plan
+    int l = 0;
+};
+
+// Default block size for a dtype (complex64 / complex128).
+int default_block_qubits(int dtype);
+int max_block_qubits(int dtype);
+
+// Build the 2x2 FP64 matrix and class of an sv_gate-like record. Returns
+// false for an unknown op.
+bool gate_matrix(int op, double theta, const double *u_in, double *u_out, int *cls);
+
+// Validate and plan. gates: raw records (op, target, control, target2,
+// theta, u[8]) laid out as sv_gate. l2p: layout at entry (size n), updated
+// copy in plan.l2p_after. Returns "" or an error message.
+struct RawGate {
+    int32_t op, target, control, target2;
+    double theta;
+    double u[8];
+};
+std::string validate(int n, const RawGate *gates, size_t m);
+std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
+                      const std::vector<int> &l2p, Plan &plan);
+
+}  // namespace svp

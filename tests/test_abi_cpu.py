@@ -1,0 +1,157 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+- the shared library loads and exports every function include/sv.h declares;
+- argument validation and error statuses;
+- the planner's SWAP and flush counts for the paper's schedule (LRU victim,
+  data-moving SWAP, target decides) equal those of the oracle's literal
+  partitioned run, under the same reading of the paper;
+- invariants of the other schedules.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_15098_amd import sv
+from paper_2605_15098_amd import workloads as W
+
+
+def test_library_exports_header():
+    lib = sv.load()
+    names = sv.header_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert "gfx950" in sv.sv_version()
+
+
+def _bad(rows, n=4):
+    return W.gates_from_tuples(rows)
+
+
+@pytest.mark.parametrize("rows,why", [
+    ([("H", 4, -1, 0.0)], "target out of range"),
+    ([("X", 1, 1, 0.0)], "control equals target"),
+    ([("RX", 0, -1, float("nan"))], "non-finite"),
+    ([("P", 0, 7, 0.1)], "control out of range"),
+])
+def test_invalid_gates_rejected(rows, why):
+    g = _bad(rows)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(4, "c64", g, sv.schedule())
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
+    assert why in e.value.message
+
+
+def test_unknown_op_and_swap_with_control():
+    g = W.gates_from_tuples([("H", 0, -1, 0.0)])
+    g[0]["op"] = 42
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(3, "c64", g)
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
+    g = W.gates_from_tuples([("SWAP", 0, 1, 0.0, 2)])
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(3, "c64", g)
+    assert "SWAP" in e.value.message
+
+
+def test_schedule_errors():
+    g = W.qpe_gates(6, 0.25)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=7))
+    assert e.value.status == sv.SV_ERR_UNSUPPORTED
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(6, "c64", g, sv.schedule(block_qubits=15))
+    assert e.value.status == sv.SV_ERR_UNSUPPORTED
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(0, "c64", g)
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
+    s = sv.schedule()
+    s.mode = 5
+    with pytest.raises(sv.SvError):
+        sv.sv_plan(6, "c64", g, s)
+
+
+def test_handles_without_gpu_fail_cleanly():
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_create(0, "c64")
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
+    sv.sv_destroy(0)  # NULL is accepted
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_reset(12345)
+    assert e.value.status == sv.SV_ERR_BAD_HANDLE
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_destroy(12345)
+    assert e.value.status == sv.SV_ERR_BAD_HANDLE
+
+
+def test_fault_injection_alloc():
+    sv.sv_debug_inject_fault(1)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_create(10, "c64")
+    assert e.value.status == sv.SV_ERR_OUT_OF_MEMORY
+    with pytest.raises(sv.SvError):
+        sv.sv_debug_inject_fault(9)
+    sv.sv_debug_inject_fault(0)
+
+
+@pytest.mark.parametrize("n,l", [(8, 3), (9, 4), (10, 6), (12, 5), (12, 9), (14, 11)])
+def test_paper_schedule_counts_match_oracle_qpe(n, l):
+    g = W.qpe_gates(n, 0.377)
+    st = sv.sv_plan(n, "c128", g, sv.paper_schedule(l))
+    _, swaps, phases, _ = oracle.apply_partitioned(n, l, g)
+    assert st["swaps"] == swaps
+    assert st["phases"] == phases
+    assert st["passes"] == swaps + phases
+    assert st["gates"] == W.qpe_gate_count(n)[0]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_paper_schedule_counts_match_oracle_random(seed):
+    rng = np.random.default_rng(seed)
+    n = 9
+    g = W.random_mixed_circuit(n, 150, rng)
+    for l in (2, 4, 6, 8):
+        st = sv.sv_plan(n, "c64", g, sv.paper_schedule(l))
+        _, swaps, phases, _ = oracle.apply_partitioned(n, l, g)
+        assert (st["swaps"], st["phases"]) == (swaps, phases), l
+
+
+def test_virtual_lru_without_pins_matches_paper_counts(monkeypatch):
+    monkeypatch.setenv("SV_PIN_BITS", "0")
+    n, l = 12, 6
+    g = W.qpe_gates(n, 0.61)
+    a = sv.sv_plan(n, "c64", g, sv.schedule(block_qubits=l, swap_policy="lru", diag_free=False))
+    _, swaps, phases, _ = oracle.apply_partitioned(n, l, g)
+    assert (a["swaps"], a["phases"]) == (swaps, phases)
+    # virtual remap moves no data: one pass per flush
+    assert a["passes"] == phases
+
+
+def test_schedule_pass_counts_and_bytes():
+    for n in (20, 28, 32):
+        g = W.qpe_gates(n, 0.123)
+        ng = W.qpe_gate_count(n)[0]
+        plain = sv.sv_plan(n, "c64", g, sv.schedule("plain"))
+        assert plain["passes"] == ng and plain["swaps"] == 0
+        paper = sv.sv_plan(n, "c64", g, sv.paper_schedule(13))
+        best = sv.sv_plan(n, "c64", g, sv.schedule(block_qubits=13))
+        assert best["passes"] < paper["passes"] < plain["passes"]
+        full = 2 * 8 * 2.0 ** n
+        assert best["bytes"] == best["passes"] * full
+        assert plain["bytes"] <= plain["passes"] * full
+    # whole circuit in one block when the state fits
+    g = W.qpe_gates(10, 37 / 512)
+    st = sv.sv_plan(10, "c128", g, sv.schedule())
+    assert st["passes"] == 1 and st["block_qubits"] == 10
+
+
+def test_empty_and_swap_only_circuits():
+    g = W.gates_from_tuples([])
+    st = sv.sv_plan(5, "c64", g)
+    assert st["passes"] == 0 and st["gates"] == 0
+    g = W.gates_from_tuples([("SWAP", 0, -1, 0.0, 3), ("SWAP", 1, -1, 0.0, 2)])
+    for s in (sv.schedule("plain"), sv.schedule(), sv.paper_schedule(3)):
+        st = sv.sv_plan(5, "c64", g, s)
+        assert st["passes"] == 0
