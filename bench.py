@@ -200,7 +200,7 @@ def main():
         "config": {
             "workload": f"qpe-{n}q-{'complex64' if args.dtype == 'c64' else 'complex128'}-partitioned",
             "n_qubits": n, "counting_qubits": n - 1, "phi_seed": seed, "phi": phi,
-            "gates_per_step": ngates, "swap_relabels": n // 2 - (0 if (n - 1) % 2 else 0),
+            "gates_per_step": ngates, "swap_relabels": (n - 1) // 2,
             "schedule": {"mode": "partitioned", "block_qubits": st["block_qubits"],
                          "swap_policy": "lookahead-bulk", "remap": "virtual", "diag_free": True},
             "passes_per_step": st["passes"], "swaps_per_step": st["swaps"],
