@@ -97,8 +97,12 @@ typedef struct {
     int32_t block_qubits; /* l, local qubits per on-chip block; 0 = default   */
     int32_t outer_qubits; /* l2 > l: second tier sized for the Infinity Cache;
                              0 = off                                          */
-    int32_t fuse_k;       /* <= 1: no fusion; 2..6: fuse runs of gates on <= k
-                             qubits into one 2^k x 2^k unitary (FP64 product)  */
+    int32_t fuse_k;       /* 0: one device op per gate (bit-exact with the
+                             plain path); 1: each run of diagonal gates in a
+                             block pass becomes one phase multiply per
+                             amplitude and Hadamard normalization is applied
+                             once per pass; 2..6: also fuse runs of gates on
+                             <= k qubits into one 2^k x 2^k unitary            */
     int32_t swap_policy;  /* SV_SWAP_LRU (the paper) or SV_SWAP_LOOKAHEAD     */
     int32_t remap;        /* SV_REMAP_VIRTUAL or SV_REMAP_EXPLICIT            */
     int32_t diag_free;    /* 0: every gate's target must be local (the paper's

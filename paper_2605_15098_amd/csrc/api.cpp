@@ -75,6 +75,8 @@ struct sv_handle_s {
     std::vector<int> l2p;
     svp::K2Op *dops = nullptr;
     size_t dops_cap = 0;
+    uint8_t *dtab = nullptr;
+    size_t dtab_cap = 0;
     void *scratch = nullptr;
     size_t scratch_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -151,6 +153,7 @@ void free_handle(sv_handle_s *h)
     if (h->ev0) hipEventDestroy(h->ev0);
     if (h->ev1) hipEventDestroy(h->ev1);
     if (h->dops) hipFree(h->dops);
+    if (h->dtab) hipFree(h->dtab);
     if (h->scratch) hipFree(h->scratch);
     if (h->owns && h->buf) hipFree(h->buf);
     delete h;
@@ -208,8 +211,9 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
         return fail(SV_ERR_INVALID_ARG, "unknown swap policy");
     if (s->remap != SV_REMAP_VIRTUAL && s->remap != SV_REMAP_EXPLICIT)
         return fail(SV_ERR_INVALID_ARG, "unknown remap");
+    if (s->fuse_k < 0) return fail(SV_ERR_INVALID_ARG, "fuse_k < 0");
     if (s->fuse_k > 6) return fail(SV_ERR_UNSUPPORTED, "fuse_k above 6");
-    if (s->fuse_k > 1) return fail(SV_ERR_UNSUPPORTED, "fusion is not available in this build");
+    if (s->fuse_k > 1) return fail(SV_ERR_UNSUPPORTED, "dense fusion is not available in this build");
     if (s->outer_qubits != 0) return fail(SV_ERR_UNSUPPORTED, "outer tier is not available in this build");
     if (s->tuner != SV_TUNER_NONE) return fail(SV_ERR_UNSUPPORTED, "tuner inside apply is not available");
     return SV_OK;
@@ -237,6 +241,23 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
                               h->stream),
                "program upload");
     }
+    if (!plan.table.empty()) {
+        const size_t need = plan.table.size();
+        if (need > h->dtab_cap) {
+            if (h->dtab) {
+                hipStreamSynchronize(h->stream);
+                hipFree(h->dtab);
+                h->dtab = nullptr;
+                h->dtab_cap = 0;
+            }
+            size_t cap = std::max<size_t>(need, 1 << 16);
+            void *p = nullptr;
+            if (dev_alloc(&p, cap) != hipSuccess) return fail(SV_ERR_OUT_OF_MEMORY, "table allocation failed");
+            h->dtab = (uint8_t *)p;
+            h->dtab_cap = cap;
+        }
+        SV_HIP(hipMemcpyAsync(h->dtab, plan.table.data(), need, hipMemcpyHostToDevice, h->stream), "table upload");
+    }
     h->kev_kind.clear();
     if (h->kernel_timing) {
         const size_t need = 2 * plan.steps.size();
@@ -262,6 +283,10 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
             a.n = h->n;
             a.l = s.l;
             a.nops = s.op_count;
+            a.nug = s.nug;
+            a.ug_off = s.ug_off;
+            a.table = h->dtab;
+            a.vec2 = (s.l >= 2 && s.logr >= 2 && s.bits[0] == 0) ? 1 : 0;
             std::vector<bool> in(h->n, false);
             for (int i = 0; i < s.l; ++i) {
                 a.bits[i] = (int8_t)s.bits[i];
@@ -292,7 +317,7 @@ void fill_stats(sv_stats *o, const svp::PlanConfig &c, const svp::Plan &p)
     o->fused = p.stats.fused;
     o->bytes = p.stats.bytes;
     o->block_qubits = p.l;
-    o->fuse_k = c.fuse_k > 1 ? c.fuse_k : 1;
+    o->fuse_k = c.fuse_k;
     o->swap_policy = c.policy;
     o->mode = c.mode;
 }

@@ -59,6 +59,16 @@ template <typename C> __device__ __forceinline__ C cmad2(C u0, C a, C u1, C b)
     return r;
 }
 
+// Component-wise select (a whole-struct ?: on double2 is lowered through
+// scratch memory).
+template <typename C> __device__ __forceinline__ C csel(bool p, C x, C y)
+{
+    C r;
+    r.x = p ? x.x : y.x;
+    r.y = p ? x.y : y.y;
+    return r;
+}
+
 // Hadamard butterfly: ((a+b)/sqrt2, (a-b)/sqrt2)
 template <typename C> __device__ __forceinline__ void hbfly(C &a, C &b)
 {
@@ -168,8 +178,7 @@ k1_diag_kernel(C *__restrict__ S, uint64_t namps, int nones, int lo, int hi, int
         if (nones >= 2) j = insert0(j, hi);
         j |= ones;
         C a = S[j];
-        C d = d1;
-        if (tsel >= 0 && !((j >> tsel) & 1ull)) d = d0;
+        const C d = csel(tsel >= 0 && !((j >> tsel) & 1ull), d0, d1);
         S[j] = cmul(d, a);
     }
 }
@@ -241,13 +250,29 @@ hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st)
 
 // LDS index swizzle: the low bits that span one 128-byte bank row are XORed
 // with a fold of the higher bits, so lanes whose local indices differ only in
-// high bits still spread over the banks. A bijection on [0, 2^l).
-template <typename C> __device__ __forceinline__ uint32_t swz(uint32_t x)
+// high bits still spread over the banks. The map is linear over GF(2) (shifts,
+// XORs and a constant mask), so for disjoint bit sets
+// swz(a | b) = swz(a) ^ swz(b): a thread swizzles its own bits once and each
+// register slot adds a block-uniform term.
+template <typename C> __host__ __device__ __forceinline__ uint32_t swz(uint32_t x)
 {
     constexpr int E = (sizeof(C) == 8) ? 4 : 3;  // log2(elements per 128 B)
     constexpr uint32_t M = (1u << E) - 1u;
     const uint32_t h = x >> E;
     return x ^ ((h ^ (h >> E) ^ (h >> (2 * E))) & M);
+}
+
+__device__ __forceinline__ uint32_t insert0_32(uint32_t x, int b)
+{
+    return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u));
+}
+
+// Non-register condition bits are coded as: 0..l-1 = local bit (tested on the
+// thread's local index), 64 + p = memory bit p outside the block (tested on
+// the block base).
+__device__ __forceinline__ bool code_bit(uint32_t tloc, uint64_t base, int code)
+{
+    return code >= 64 ? (bool)((base >> (code - 64)) & 1ull) : (bool)((tloc >> code) & 1u);
 }
 
 template <int J, int R, typename C>
@@ -265,6 +290,11 @@ __device__ __forceinline__ void k2_pairs(C *a, int kind, const double *v, bool t
             nx = x;
             ny = y;
             hbfly(nx, ny);
+        } else if (kind == svp::K2_HU) {
+            nx.x = x.x + y.x;
+            nx.y = x.y + y.y;
+            ny.x = x.x - y.x;
+            ny.y = x.y - y.y;
         } else if (kind == svp::K2_X) {
             nx = y;
             ny = x;
@@ -272,19 +302,33 @@ __device__ __forceinline__ void k2_pairs(C *a, int kind, const double *v, bool t
             nx = cmad2(u00, x, u01, y);
             ny = cmad2(u10, x, u11, y);
         }
-        a[k] = tpred ? nx : x;
-        a[k + H] = tpred ? ny : y;
+        a[k] = csel(tpred, nx, x);
+        a[k + H] = csel(tpred, ny, y);
     }
 }
 
+// Block-resident pass. Work-group = one block of 2^l amplitudes: local bit i
+// is memory bit args.bits[i]; the other memory bits come from blockIdx. Each
+// thread holds R = 2^LOGR amplitudes in registers; register slot j stands for
+// local bit rb[j]; the remaining local bits, in ascending order, are the bits
+// of threadIdx. The program (args.nops ops) starts and ends in the canonical
+// layout: slot 0 = local bit 0, slots 1.. = the top LOGR-1 local bits, so
+// lanes walk consecutive memory and, for complex64, slots 0 and 1 form one
+// 16-byte access.
+// Largest work-group of a block-pass variant: big register tiles need the
+// VGPR budget of fewer waves per SIMD.
+template <typename T, int LOGR> constexpr int k2_max_threads()
+{
+    return (LOGR + (sizeof(T) == 8 ? 1 : 0)) >= 5 ? (LOGR + (sizeof(T) == 8 ? 1 : 0) >= 6 ? 256 : 512) : 1024;
+}
+
 template <typename T, int LOGR>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
 k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, K2Args args)
 {
     using C = typename CT<T>::type;
     constexpr int R = 1 << LOGR;
     extern __shared__ unsigned char lds_raw[];
-    C *lds = reinterpret_cast<C *>(lds_raw);
     const int l = args.l;
     const int tb = l - LOGR;
     const uint32_t tid = threadIdx.x;
@@ -294,21 +338,54 @@ k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ op
         const uint64_t bid = blockIdx.x;
         for (int i = 0; i < args.n - l; ++i) base |= ((bid >> i) & 1ull) << args.nbits[i];
     }
+    // Block-uniform phase factors of the diagonal runs: each is
+    // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in 64-bit
+    // fixed-point turns and evaluated once per work-group.
+    double2 *ufac = reinterpret_cast<double2 *>(lds_raw + (sizeof(C) << l));
+    if (args.nug > 0) {
+        const svp::UGroup *ug = reinterpret_cast<const svp::UGroup *>(args.table + args.ug_off);
+        for (int g = threadIdx.x; g < args.nug; g += blockDim.x) {
+            const svp::UTerm *tm = reinterpret_cast<const svp::UTerm *>(args.table + ug[g].term_off);
+            uint64_t acc = 0;
+            for (int j = 0; j < ug[g].nterms; ++j)
+                if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
+            double sn, cs;
+            sincospi(ldexp((double)(int64_t)acc, -63), &sn, &cs);
+            ufac[g] = make_double2(cs, sn);
+        }
+        __syncthreads();
+    }
+
     int rb[LOGR];
+    rb[0] = 0;
 #pragma unroll
-    for (int j = 0; j < LOGR; ++j) rb[j] = tb + j;
-    uint32_t tloc = tid;
-    uint64_t tmem = base;
-    for (int i = 0; i < tb; ++i) tmem |= (uint64_t)((tid >> i) & 1u) << args.bits[i];
+    for (int j = 1; j < LOGR; ++j) rb[j] = tb + j;
+    uint32_t tloc = tid << 1;
+
+    // memory index of the thread's slot-0 amplitude in the canonical layout
+    uint64_t tmem0 = base;
+    for (int i = 0; i < tb; ++i) tmem0 |= (uint64_t)((tid >> i) & 1u) << args.bits[i + 1];
+    uint64_t roff[LOGR];
+#pragma unroll
+    for (int j = 0; j < LOGR; ++j) roff[j] = 1ull << args.bits[rb[j]];
 
     C a[R];
-    {
-        uint64_t roff[LOGR];
+    if (sizeof(C) == 8 && args.vec2) {
+        // memory bit 0 is local bit 0 = slot 0: slots k, k+1 are adjacent
 #pragma unroll
-        for (int j = 0; j < LOGR; ++j) roff[j] = 1ull << args.bits[rb[j]];
+        for (int k = 0; k < R; k += 2) {
+            uint64_t addr = tmem0;
+#pragma unroll
+            for (int j = 1; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            const float4 v = *reinterpret_cast<const float4 *>(S + addr);
+            a[k] = mk<C>(v.x, v.y);
+            a[k + 1] = mk<C>(v.z, v.w);
+        }
+    } else {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            uint64_t addr = tmem;
+            uint64_t addr = tmem0;
 #pragma unroll
             for (int j = 0; j < LOGR; ++j)
                 if ((k >> j) & 1) addr += roff[j];
@@ -320,77 +397,114 @@ k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ op
         const svp::K2Op &op = ops[oi];
         const int kind = op.kind;
         if (kind == svp::K2_LAYOUT) {
+            {
+                const uint32_t tsw = swz<C>(tloc) * (uint32_t)sizeof(C);
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                uint32_t x = tloc;
+                for (int k = 0; k < R; ++k) {
+                    uint32_t kp = 0;
 #pragma unroll
-                for (int j = 0; j < LOGR; ++j)
-                    if ((k >> j) & 1) x |= 1u << rb[j];
-                lds[swz<C>(x)] = a[k];
+                    for (int j = 0; j < LOGR; ++j)
+                        if ((k >> j) & 1) kp |= 1u << rb[j];
+                    *reinterpret_cast<C *>(lds_raw + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C)))) = a[k];
+                }
             }
             __syncthreads();
-            uint32_t rmask = 0;
+            uint32_t x = tid;
 #pragma unroll
             for (int j = 0; j < LOGR; ++j) {
                 rb[j] = (op.a >> (5 * j)) & 31;
-                rmask |= 1u << rb[j];
+                x = insert0_32(x, rb[j]);  // rb ascending: zeros land on register bits
             }
-            tloc = 0;
-            tmem = base;
-            int cnt = 0;
-            for (int i = 0; i < l; ++i) {
-                if ((rmask >> i) & 1u) continue;
-                const uint32_t bit = (tid >> cnt) & 1u;
-                tloc |= bit << i;
-                tmem |= (uint64_t)bit << args.bits[i];
-                ++cnt;
+            tloc = x;
+            {
+                const uint32_t tsw = swz<C>(tloc) * (uint32_t)sizeof(C);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    uint32_t kp = 0;
+#pragma unroll
+                    for (int j = 0; j < LOGR; ++j)
+                        if ((k >> j) & 1) kp |= 1u << rb[j];
+                    a[k] = *reinterpret_cast<const C *>(lds_raw + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C))));
+                }
+            }
+            __syncthreads();
+        } else if (kind == svp::K2_DIAGRUN) {
+            // one phase multiply per amplitude for a whole run of diagonal
+            // gates: F(k) = Q[k] * prod of the thread factors whose slot mask
+            // k covers; factors assembled in FP64, rounded once
+            const svp::DiagRec *rec = reinterpret_cast<const svp::DiagRec *>(args.table + op.a);
+            const double2 *qt = reinterpret_cast<const double2 *>(rec + 1);
+            const int ng = rec->ngroups;
+            const uint64_t kmask = rec->kmask;
+            double2 f[svp::DIAG_MAX_GROUPS];
+            int rm[svp::DIAG_MAX_GROUPS];
+#pragma unroll
+            for (int g = 0; g < svp::DIAG_MAX_GROUPS; ++g) {
+                f[g] = make_double2(1.0, 0.0);
+                rm[g] = 0;
+                if (g >= ng) continue;
+                const svp::DiagGroup &G = rec->g[g];
+                rm[g] = G.rmask;
+                bool on = true;
+                if (G.cond_kind == 1) on = (base >> G.cond_bit) & 1ull;
+                else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1u;
+                if (!on) continue;
+                double2 v = make_double2(1.0, 0.0);  // groups off by condition keep 1
+                if (G.uidx >= 0) v = ufac[G.uidx];
+                if (G.wave_off >= 0) v = cmul(v, reinterpret_cast<const double2 *>(args.table + G.wave_off)[tid >> 6]);
+                if (G.lane_off >= 0) v = cmul(v, reinterpret_cast<const double2 *>(args.table + G.lane_off)[tid & 63u]);
+                f[g] = v;
             }
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                uint32_t x = tloc;
+                if (!((kmask >> k) & 1ull)) continue;
+                double2 F = qt[k];
 #pragma unroll
-                for (int j = 0; j < LOGR; ++j)
-                    if ((k >> j) & 1) x |= 1u << rb[j];
-                a[k] = lds[swz<C>(x)];
+                for (int g = 0; g < svp::DIAG_MAX_GROUPS; ++g)
+                    if (g < ng && (rm[g] & k) == rm[g]) F = cmul(F, f[g]);
+                a[k] = cmul(mk<C>(F.x, F.y), a[k]);
             }
-            __syncthreads();
+        } else if (kind == svp::K2_SCALE) {
+            const T sc = (T)op.v[0];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                a[k].x *= sc;
+                a[k].y *= sc;
+            }
         } else if (kind == svp::K2_PHASE) {
-            const bool tpred = (tmem & op.m0) == op.m0;
+            const bool tpred = ((tloc & (uint32_t)op.m0) == (uint32_t)op.m0) && ((base & op.m1) == op.m1);
             const C z = mk<C>(op.v[0], op.v[1]);
             const int rmask = op.a;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 if ((k & rmask) != rmask) continue;
-                const C y = cmul(z, a[k]);
-                a[k] = tpred ? y : a[k];
+                a[k] = csel(tpred, cmul(z, a[k]), a[k]);
             }
         } else if (kind == svp::K2_DIAG) {
-            const bool tpred = (tmem & op.m0) == op.m0;
+            const bool tpred = ((tloc & (uint32_t)op.m0) == (uint32_t)op.m0) && ((base & op.m1) == op.m1);
             const C d0 = mk<C>(op.v[0], op.v[1]), d1 = mk<C>(op.v[2], op.v[3]);
             const int slot = op.a, rmask = op.c;
             if (slot >= 0) {
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     if ((k & rmask) != rmask) continue;
-                    const C d = ((k >> slot) & 1) ? d1 : d0;
-                    const C y = cmul(d, a[k]);
-                    a[k] = tpred ? y : a[k];
+                    const C d = csel(((k >> slot) & 1) != 0, d1, d0);
+                    a[k] = csel(tpred, cmul(d, a[k]), a[k]);
                 }
             } else {
-                const bool sel = (tmem >> op.b) & 1ull;
+                const bool sel = code_bit(tloc, base, op.b);
                 C d;
                 d.x = sel ? d1.x : d0.x;
                 d.y = sel ? d1.y : d0.y;
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     if ((k & rmask) != rmask) continue;
-                    const C y = cmul(d, a[k]);
-                    a[k] = tpred ? y : a[k];
+                    a[k] = csel(tpred, cmul(d, a[k]), a[k]);
                 }
             }
         } else {
             const int ckind = op.b;
-            const bool tpred = (ckind == svp::CK_MEM) ? (bool)((tmem >> op.c) & 1ull) : true;
+            const bool tpred = (ckind == svp::CK_MEM) ? code_bit(tloc, base, op.c) : true;
             const int cslot = op.c;
             switch (op.a) {
             case 0: k2_pairs<0, R>(a, kind, op.v, tpred, ckind, cslot); break;
@@ -403,14 +517,25 @@ k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ op
         }
     }
 
-    {
-        // the program ends in the canonical layout: registers = top local bits
-        uint64_t roff[LOGR];
+    // the program ends in the canonical layout
+    if (sizeof(C) == 8 && args.vec2) {
 #pragma unroll
-        for (int j = 0; j < LOGR; ++j) roff[j] = 1ull << args.bits[rb[j]];
+        for (int k = 0; k < R; k += 2) {
+            uint64_t addr = tmem0;
+#pragma unroll
+            for (int j = 1; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            float4 v;
+            v.x = (float)a[k].x;
+            v.y = (float)a[k].y;
+            v.z = (float)a[k + 1].x;
+            v.w = (float)a[k + 1].y;
+            *reinterpret_cast<float4 *>(S + addr) = v;
+        }
+    } else {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            uint64_t addr = tmem;
+            uint64_t addr = tmem0;
 #pragma unroll
             for (int j = 0; j < LOGR; ++j)
                 if ((k >> j) & 1) addr += roff[j];
@@ -423,7 +548,7 @@ template <typename T, int LOGR>
 static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hipStream_t st)
 {
     using C = typename CT<T>::type;
-    const size_t lds = (size_t)sizeof(C) << a.l;
+    const size_t lds = ((size_t)sizeof(C) << a.l) + (size_t)a.nug * sizeof(double2);
     static size_t attr_bytes = 64 * 1024;
     if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k2_kernel<T, LOGR>,
@@ -433,7 +558,8 @@ static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hi
     }
     const unsigned threads = 1u << (a.l - LOGR);
     const uint64_t blocks = 1ull << (a.n - a.l);
-    if (threads > 1024 || blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+    if (threads > (unsigned)k2_max_threads<T, LOGR>() || blocks > 0x7fffffffull)
+        return hipErrorInvalidConfiguration;
     k2_kernel<T, LOGR><<<(unsigned)blocks, threads, lds, st>>>((C *)S, ops, a);
     return hipGetLastError();
 }
@@ -454,7 +580,7 @@ static hipError_t k2_dispatch(void *S, int logr, const K2Args &a, const svp::K2O
 hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *ops,
                    hipStream_t st)
 {
-    if (a.l < logr || a.l > n) return hipErrorInvalidValue;
+    if (a.l < logr || a.l > n || logr < 1) return hipErrorInvalidValue;
     return dtype == 0 ? k2_dispatch<float>(S, logr, a, ops, st)
                       : k2_dispatch<double>(S, logr, a, ops, st);
 }

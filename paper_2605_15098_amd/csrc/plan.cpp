@@ -44,6 +44,35 @@ bool gate_matrix(int op, double theta, const double *u_in, double *u, int *cls)
     return true;
 }
 
+uint64_t turns_fixed(double turns)
+{
+    double r = turns - std::floor(turns);  // [0, 1]
+    if (r >= 1.0) r = 0.0;
+    return (uint64_t)std::ldexp(r, 64);
+}
+
+// Angles (turns) of the two diagonal entries of a diagonal gate, exact for
+// the gate kinds defined by an angle. Entries that are not of unit modulus
+// mark the gate as non-unit.
+static void diag_angles(const RawGate &x, MGate &g)
+{
+    g.unit = 0;
+    g.th0 = g.th1 = 0.0;
+    if (g.cls != GC_DIAG) return;
+    const double tw = 1.0 / (2.0 * M_PI);
+    switch (x.op) {
+    case OP_Z: g.th1 = 0.5; g.unit = 1; return;
+    case OP_P: g.th1 = x.theta * tw; g.unit = 1; return;
+    case OP_RZ: g.th0 = -0.5 * x.theta * tw; g.th1 = 0.5 * x.theta * tw; g.unit = 1; return;
+    default: break;
+    }
+    const double m0 = std::hypot(g.u[0], g.u[1]), m1 = std::hypot(g.u[6], g.u[7]);
+    if (std::fabs(m0 - 1.0) > 1e-14 || std::fabs(m1 - 1.0) > 1e-14) return;
+    g.th0 = std::atan2(g.u[1], g.u[0]) * tw;
+    g.th1 = std::atan2(g.u[7], g.u[6]) * tw;
+    g.unit = 1;
+}
+
 std::string validate(int n, const RawGate *g, size_t m)
 {
     if (m > 0 && !g) return "gate array is null";
@@ -108,14 +137,198 @@ struct Builder {
     }
 
     // ---- block-pass compilation ---------------------------------------
+
+    // Append raw bytes to the table buffer at a 16-byte aligned offset.
+    int table_put(const void *p, size_t bytes)
+    {
+        size_t off = (plan.table.size() + 15) & ~size_t(15);
+        plan.table.resize(off + bytes);
+        std::memcpy(plan.table.data() + off, p, bytes);
+        return (int)off;
+    }
+
+    // One diagonal term: the amplitude gains angle turns (fixed point) when
+    // every register slot of rmask and every memory bit of tmask is 1.
+    struct Term {
+        int rmask;
+        uint64_t tmask;
+        uint64_t angle;
+    };
+
+    // Emit a run of diagonal gates as K2_DIAGRUN ops for the current layout.
+    // Returns false when a gate has non-unit entries (caller emits K2_DIAG).
+    void emit_diag_run(const std::vector<MGate> &run, const std::vector<int> &rank,
+                       const std::vector<int> &rb, std::vector<UGroup> &ugroups,
+                       std::vector<UTerm> &uterms)
+    {
+        const int r = logr;
+        // thread-id bit of each non-register local bit (lanes: 0..5)
+        std::vector<int> tbit(64, -1);
+        {
+            std::vector<bool> isreg(l, false);
+            for (int j = 0; j < r; ++j) isreg[rb[j]] = true;
+            int cnt = 0;
+            for (int i = 0; i < l; ++i)
+                if (!isreg[i]) tbit[i] = cnt++;
+        }
+        const int nthread_bits = l - r;
+        const int nwave_bits = nthread_bits > 6 ? nthread_bits - 6 : 0;
+        auto slot_of_mem = [&](int p) -> int {
+            const int lb = rank[p];
+            if (lb < 0) return -1;
+            for (int j = 0; j < r; ++j)
+                if (rb[j] == lb) return j;
+            return -1;
+        };
+        std::vector<Term> terms;
+        auto add = [&](std::vector<int> bits, double turns) {
+            Term t{0, 0, turns_fixed(turns)};
+            if (t.angle == 0) return;
+            for (int p : bits) {
+                const int s = slot_of_mem(p);
+                if (s >= 0) t.rmask |= 1 << s;
+                else t.tmask |= 1ull << p;
+            }
+            terms.push_back(t);
+        };
+        for (const MGate &g : run) {
+            std::vector<int> cb;
+            if (g.c >= 0) cb.push_back(g.c);
+            add(cb, g.th0);
+            cb.push_back(g.t);
+            add(cb, g.th1 - g.th0);
+        }
+        // classify the memory bits of a term's thread part
+        enum { CL_LANE = 0, CL_WAVE = 1, CL_GLOBAL = 2 };
+        auto cls = [&](int p) {
+            const int lb = rank[p];
+            if (lb < 0) return (int)CL_GLOBAL;
+            return tbit[lb] < 6 ? (int)CL_LANE : (int)CL_WAVE;
+        };
+        struct GroupAcc {
+            int rmask, cond_kind, cond_bit;
+            std::vector<std::pair<uint64_t, uint64_t>> lane, wave, glob;  // (mask, angle)
+        };
+        std::vector<GroupAcc> groups;
+        std::vector<uint64_t> qang(size_t(1) << r, 0);
+        for (const Term &t : terms) {
+            if (t.tmask == 0) {
+                for (size_t k = 0; k < qang.size(); ++k)
+                    if ((int(k) & t.rmask) == t.rmask) qang[k] += t.angle;
+                continue;
+            }
+            std::vector<int> bits;
+            for (int p = 0; p < 64; ++p)
+                if ((t.tmask >> p) & 1ull) bits.push_back(p);
+            int ck = 0, cbit = 0;
+            uint64_t rest = t.tmask;
+            if (bits.size() == 2 && cls(bits[0]) != cls(bits[1])) {
+                // the non-lane bit (global before wave) becomes a condition
+                int a = bits[0], b2 = bits[1];
+                int pick = (cls(a) == CL_GLOBAL) ? a : (cls(b2) == CL_GLOBAL ? b2 : (cls(a) == CL_WAVE ? a : b2));
+                if (cls(pick) == CL_GLOBAL) { ck = 1; cbit = pick; }
+                else { ck = 2; cbit = tbit[rank[pick]]; }
+                rest &= ~(1ull << pick);
+            }
+            int part = -1;
+            for (int p = 0; p < 64; ++p)
+                if ((rest >> p) & 1ull) part = cls(p);
+            GroupAcc *G = nullptr;
+            for (auto &x : groups)
+                if (x.rmask == t.rmask && x.cond_kind == ck && x.cond_bit == cbit) G = &x;
+            if (!G) {
+                groups.push_back(GroupAcc{t.rmask, ck, cbit, {}, {}, {}});
+                G = &groups.back();
+            }
+            if (part == CL_LANE) G->lane.push_back({rest, t.angle});
+            else if (part == CL_WAVE) G->wave.push_back({rest, t.angle});
+            else G->glob.push_back({rest, t.angle});
+        }
+        auto cexp = [](uint64_t a, double *out) {
+            const double x = std::ldexp((double)(int64_t)a, -63);  // half-turns in [-1, 1)
+            out[0] = std::cos(M_PI * x);
+            out[1] = std::sin(M_PI * x);
+        };
+        // tables over lane / wave thread-id bits
+        auto build_table = [&](const std::vector<std::pair<uint64_t, uint64_t>> &ts, int first, int nbits) {
+            const int N = 1 << nbits;
+            std::vector<double> tab(2 * std::max(N, 1));
+            for (int x = 0; x < N; ++x) {
+                uint64_t acc = 0;
+                for (auto &pr : ts) {
+                    bool on = true;
+                    for (int p = 0; p < 64; ++p)
+                        if ((pr.first >> p) & 1ull) {
+                            const int tb = tbit[rank[p]] - first;
+                            if (!((x >> tb) & 1)) on = false;
+                        }
+                    if (on) acc += pr.second;
+                }
+                cexp(acc, &tab[2 * x]);
+            }
+            return table_put(tab.data(), tab.size() * sizeof(double));
+        };
+        size_t gi = 0;
+        bool first = true;
+        while (first || gi < groups.size()) {
+            DiagRec rec{};
+            const size_t take = std::min<size_t>(DIAG_MAX_GROUPS, groups.size() - gi);
+            rec.ngroups = (int)take;
+            std::vector<double> q(2 * qang.size());
+            for (size_t k = 0; k < qang.size(); ++k) {
+                const uint64_t a = first ? qang[k] : 0;
+                cexp(a, &q[2 * k]);
+                if (a != 0) rec.kmask |= 1ull << k;
+            }
+            for (size_t j = 0; j < take; ++j) {
+                GroupAcc &G = groups[gi + j];
+                DiagGroup &d = rec.g[j];
+                d.rmask = G.rmask;
+                d.cond_kind = G.cond_kind;
+                d.cond_bit = G.cond_bit;
+                d.uidx = -1;
+                d.lane_off = -1;
+                d.wave_off = -1;
+                if (!G.lane.empty()) d.lane_off = build_table(G.lane, 0, std::min(6, nthread_bits));
+                if (!G.wave.empty()) d.wave_off = build_table(G.wave, 6, nwave_bits);
+                if (!G.glob.empty()) {
+                    UGroup ug{(int)uterms.size(), (int)G.glob.size()};
+                    for (auto &pr : G.glob) uterms.push_back(UTerm{pr.first, pr.second});
+                    d.uidx = (int)ugroups.size();
+                    ugroups.push_back(ug);
+                }
+                for (size_t k = 0; k < qang.size(); ++k)
+                    if ((int(k) & G.rmask) == G.rmask) rec.kmask |= 1ull << k;
+            }
+            if (rec.kmask != 0) {
+                std::vector<uint8_t> blob(sizeof(DiagRec) + q.size() * sizeof(double));
+                std::memcpy(blob.data(), &rec, sizeof(DiagRec));
+                std::memcpy(blob.data() + sizeof(DiagRec), q.data(), q.size() * sizeof(double));
+                K2Op op{};
+                op.kind = K2_DIAGRUN;
+                op.a = table_put(blob.data(), blob.size());
+                op.b = (int)take;
+                plan.ops.push_back(op);
+            }
+            gi += take;
+            first = false;
+        }
+    }
+
     void compile_block(const std::vector<MGate> &q, const std::vector<int> &B)
     {
         const int r = logr;
+        const bool combine = cfg.fuse_k >= 1;
         std::vector<int> rank(64, -1);
         for (int i = 0; i < (int)B.size(); ++i) rank[B[i]] = i;
+        // canonical layout (load and store): slot 0 = local bit 0, the other
+        // slots = the top local bits
         std::vector<int> canon(r);
-        for (int j = 0; j < r; ++j) canon[j] = l - r + j;
+        canon[0] = 0;
+        for (int j = 1; j < r; ++j) canon[j] = l - r + j;
         std::vector<int> rb = canon;  // register slot j holds local bit rb[j]
+        std::vector<UGroup> ugroups;
+        std::vector<UTerm> uterms;
         auto slot_of = [&](int local) {
             for (int j = 0; j < r; ++j)
                 if (rb[j] == local) return j;
@@ -132,46 +345,77 @@ struct Builder {
             plan.ops.push_back(op);
             rb = nrb;
         };
+        // a non-register bit as the kernel tests it: local bit index, or
+        // 64 + memory bit for a bit of the block base
+        auto code_of = [&](int p) { return rank[p] >= 0 ? rank[p] : 64 + p; };
+        auto emit_single_diag = [&](const MGate &g) {
+            K2Op op{};
+            const bool ptype = (g.u[0] == 1.0 && g.u[1] == 0.0);
+            int rmask = 0;
+            uint64_t lmask = 0, gmask = 0;
+            auto cond = [&](int p) {
+                const int lb = rank[p];
+                const int sl = lb >= 0 ? slot_of(lb) : -1;
+                if (sl >= 0) rmask |= 1 << sl;
+                else if (lb >= 0) lmask |= 1ull << lb;
+                else gmask |= 1ull << p;
+            };
+            if (g.c >= 0) cond(g.c);
+            if (ptype) {
+                cond(g.t);
+                op.kind = K2_PHASE;
+                op.a = rmask;
+                op.m0 = lmask;
+                op.m1 = gmask;
+                op.v[0] = g.u[6];
+                op.v[1] = g.u[7];
+            } else {
+                const int lb = rank[g.t];
+                const int sl = lb >= 0 ? slot_of(lb) : -1;
+                op.kind = K2_DIAG;
+                op.a = sl;
+                op.b = code_of(g.t);
+                op.c = rmask;
+                op.m0 = lmask;
+                op.m1 = gmask;
+                op.v[0] = g.u[0]; op.v[1] = g.u[1];
+                op.v[2] = g.u[6]; op.v[3] = g.u[7];
+            }
+            plan.ops.push_back(op);
+        };
+        std::vector<MGate> pending;
+        auto flush_diag = [&]() {
+            if (pending.empty()) return;
+            if (!combine) {
+                for (const MGate &g : pending) emit_single_diag(g);
+            } else {
+                std::vector<MGate> unit_run;
+                for (const MGate &g : pending) {
+                    if (g.unit) { unit_run.push_back(g); continue; }
+                    // a non-unit diagonal ends the combinable run
+                    if (!unit_run.empty()) emit_diag_run(unit_run, rank, rb, ugroups, uterms);
+                    unit_run.clear();
+                    emit_single_diag(g);
+                }
+                if (!unit_run.empty()) emit_diag_run(unit_run, rank, rb, ugroups, uterms);
+            }
+            pending.clear();
+        };
+        int hscale = 0;  // unnormalized Hadamards applied in this pass
         const int begin = (int)plan.ops.size();
         for (size_t i = 0; i < q.size(); ++i) {
             const MGate &g = q[i];
             if (g.cls == GC_DIAG) {
-                K2Op op{};
-                const bool ptype = (g.u[0] == 1.0 && g.u[1] == 0.0);
-                int rmask = 0;
-                uint64_t tmask = 0;
-                auto cond = [&](int p) {
-                    const int lb = rank[p];
-                    const int sl = lb >= 0 ? slot_of(lb) : -1;
-                    if (sl >= 0) rmask |= 1 << sl;
-                    else tmask |= 1ull << p;
-                };
-                if (g.c >= 0) cond(g.c);
-                if (ptype) {
-                    cond(g.t);
-                    op.kind = K2_PHASE;
-                    op.a = rmask;
-                    op.m0 = tmask;
-                    op.v[0] = g.u[6];
-                    op.v[1] = g.u[7];
-                } else {
-                    const int lb = rank[g.t];
-                    const int sl = lb >= 0 ? slot_of(lb) : -1;
-                    op.kind = K2_DIAG;
-                    op.a = sl;
-                    op.b = g.t;
-                    op.c = rmask;
-                    op.m0 = tmask;
-                    op.v[0] = g.u[0]; op.v[1] = g.u[1];
-                    op.v[2] = g.u[6]; op.v[3] = g.u[7];
-                }
-                plan.ops.push_back(op);
+                pending.push_back(g);
                 continue;
             }
             const int lt = rank[g.t];
             if (slot_of(lt) < 0) {
                 // new register set: this target, then the next distinct
-                // non-diagonal targets of the run, then current slots
+                // non-diagonal targets of the run, then current slots. The
+                // re-layout is placed before the pending diagonal run (pure
+                // data movement commutes with it), so the run sees this
+                // target as a register slot.
                 std::vector<int> nrb{lt};
                 for (size_t k = i + 1; k < q.size() && (int)nrb.size() < r; ++k) {
                     if (q[k].cls == GC_DIAG) continue;
@@ -184,18 +428,30 @@ struct Builder {
                     if (std::find(nrb.begin(), nrb.end(), x) == nrb.end()) nrb.push_back(x);
                 emit_layout(nrb);
             }
+            flush_diag();
             K2Op op{};
             op.kind = g.op == OP_H ? K2_H : (g.cls == GC_PERM ? K2_X : K2_DENSE);
             op.a = slot_of(lt);
             if (g.c < 0) {
                 op.b = CK_NONE;
+                if (combine && op.kind == K2_H) {
+                    op.kind = K2_HU;
+                    ++hscale;
+                }
             } else {
                 const int lc = rank[g.c];
                 const int sc = lc >= 0 ? slot_of(lc) : -1;
                 if (sc >= 0) { op.b = CK_SLOT; op.c = sc; }
-                else { op.b = CK_MEM; op.c = g.c; }
+                else { op.b = CK_MEM; op.c = code_of(g.c); }
             }
             for (int k = 0; k < 8; ++k) op.v[k] = g.u[k];
+            plan.ops.push_back(op);
+        }
+        flush_diag();
+        if (hscale > 0) {
+            K2Op op{};
+            op.kind = K2_SCALE;
+            op.v[0] = std::ldexp(1.0, -(hscale / 2)) * ((hscale & 1) ? 0.70710678118654752440 : 1.0);
             plan.ops.push_back(op);
         }
         emit_layout(canon);
@@ -207,6 +463,13 @@ struct Builder {
         s.op_begin = begin;
         s.op_count = (int)plan.ops.size() - begin;
         s.ngates = (int)q.size();
+        if (!ugroups.empty()) {
+            // term offsets become byte offsets in the table
+            const int toff = table_put(uterms.data(), uterms.size() * sizeof(UTerm));
+            for (UGroup &u : ugroups) u.term_off = toff + u.term_off * (int)sizeof(UTerm);
+            s.ug_off = table_put(ugroups.data(), ugroups.size() * sizeof(UGroup));
+            s.nug = (int)ugroups.size();
+        }
         plan.steps.push_back(s);
         plan.stats.phases += 1;
         plan.stats.passes += 1;
@@ -234,6 +497,7 @@ std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
         gate_matrix(x.op, x.theta, x.u, g.u, &g.cls);
         g.t = l2p[x.target];
         g.c = x.control >= 0 ? l2p[x.control] : -1;
+        diag_angles(x, g);
     };
     auto relabel = [&](int a, int bq) {
         const int pa = l2p[a], pb = l2p[bq];
@@ -259,6 +523,7 @@ std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
     if (l > max_block_qubits(cfg.dtype)) return "block_qubits above the on-chip maximum";
     b.l = l;
     b.logr = std::min(cfg.logr, l);
+    if (l - b.logr > 10) b.logr = l - 10;  // at most 1024 threads per block
     plan.l = l;
     const bool explicit_remap = cfg.remap == 1;
     int pin = 0;

@@ -14,9 +14,11 @@
 //
 // Device program of one block-resident pass: every work-group holds one
 // block, 2^r amplitudes per thread in registers ("register slots"), the
-// other l-r local bits spread over lanes and waves. Gates target register
-// slots; a layout op moves the block through LDS so that other local bits
-// become register slots. Diagonal gates act on any bit.
+// other l-r local bits spread over the thread id (lanes = thread-id bits
+// 0..5, waves above). Gates target register slots; a layout op moves the
+// block through LDS so that other local bits become register slots.
+// Diagonal gates act on any bit; a run of them becomes one phase multiply per
+// amplitude whose factor is assembled from host-built tables.
 #pragma once
 
 #include <cstdint>
@@ -35,21 +37,25 @@ struct MGate {
     int t;          // memory bit of the target
     int c;          // memory bit of the control, -1 for none
     double u[8];    // row-major 2x2 (re, im)
+    // diagonal gates with unit-modulus entries: d0 = e^{2 pi i th0},
+    // d1 = e^{2 pi i th1} (angles in turns); unit = 0 otherwise
+    int unit;
+    double th0, th1;
 };
 
 // Block-pass ops (device program). Field meaning per kind is documented at
 // the kernel that executes them.
 enum K2Kind {
-    K2_LAYOUT = 0, // a: packed register local bits (5 bits each)
-    K2_DENSE = 1,  // a: slot; b: control kind; c: control slot or memory bit
-    K2_H = 2,      // as K2_DENSE, fixed matrix
-    K2_X = 3,      // as K2_DENSE, exchange
-    K2_PHASE = 4,  // m0: memory-bit mask; a: slot mask; v[0..1]: factor
-    K2_DIAG = 5,   // a: target slot or -1; b: target memory bit; c: slot mask;
-                   // m0: memory-bit mask; v[0..1]: d0, v[2..3]: d1
-    K2_FUSED = 6,  // a: slot mask of the k fused bits (k = b); m0: control
-                   // memory mask; c: index of the 2^k x 2^k matrix in the
-                   // matrix table
+    K2_LAYOUT = 0,   // a: packed register local bits (5 bits each)
+    K2_DENSE = 1,    // a: slot; b: control kind; c: control slot or memory bit
+    K2_H = 2,        // as K2_DENSE, Hadamard
+    K2_X = 3,        // as K2_DENSE, exchange
+    K2_PHASE = 4,    // m0: memory-bit mask; a: slot mask; v[0..1]: factor
+    K2_DIAG = 5,     // a: target slot or -1; b: target memory bit; c: slot mask;
+                     // m0: memory-bit mask; v[0..1]: d0, v[2..3]: d1
+    K2_DIAGRUN = 6,  // a: byte offset of a DiagRec in the table buffer
+    K2_HU = 7,       // unnormalized Hadamard (a+b, a-b) on slot a, no control
+    K2_SCALE = 8,    // every amplitude times v[0]
 };
 enum CtlKind { CK_NONE = 0, CK_SLOT = 1, CK_MEM = 2 };
 
@@ -59,6 +65,42 @@ struct K2Op {
     double v[8];
 };
 static_assert(sizeof(K2Op) == 96, "K2Op layout");
+
+// One thread-dependent factor of a diagonal run: applied to the amplitudes
+// whose register slots cover rmask, when the block-uniform or wave-uniform
+// condition holds. factor = U[uidx] * wave_table[wave] * lane_table[lane].
+struct DiagGroup {
+    int32_t rmask;
+    int32_t cond_kind;  // 0 none, 1 memory bit of the block base, 2 thread-id bit (>= 6)
+    int32_t cond_bit;
+    int32_t uidx;       // block-uniform factor index, -1 none
+    int32_t lane_off;   // byte offset of 64 complex doubles, -1 none
+    int32_t wave_off;   // byte offset of 2^(waves) complex doubles, -1 none
+    int32_t pad0, pad1;
+};
+static_assert(sizeof(DiagGroup) == 32, "DiagGroup layout");
+
+constexpr int DIAG_MAX_GROUPS = 4;
+// A diagonal run; followed in the table by 2^r complex doubles: the constant
+// factor of each register pattern k.
+struct DiagRec {
+    uint64_t kmask;     // bit k: amplitude slot k needs a multiply
+    int32_t ngroups;
+    int32_t pad;
+    DiagGroup g[DIAG_MAX_GROUPS];
+};
+static_assert(sizeof(DiagRec) == 144, "DiagRec layout");
+
+// Block-uniform factor: e^{2 pi i sum angle_j [base covers tmask_j]} with
+// angles as 64-bit fixed-point turns; computed once per work-group.
+struct UGroup {
+    int32_t term_off;   // byte offset of the UTerm array
+    int32_t nterms;
+};
+struct UTerm {
+    uint64_t tmask;
+    uint64_t angle;
+};
 
 enum StepKind {
     ST_K1 = 0,  // one plain sweep for one gate
@@ -73,6 +115,7 @@ struct Step {
     int logr = 0;           // ST_K2: register bits per thread
     int bits[64] = {0};     // ST_K2: memory bit of each local bit (ascending)
     int op_begin = 0, op_count = 0;
+    int ug_off = 0, nug = 0;  // ST_K2: block-uniform factor groups
     int p = 0, v = 0;       // ST_K3
     int ngates = 0;         // gates applied by this step
 };
@@ -87,7 +130,8 @@ struct PlanConfig {
     int remap = 0;            // 0 virtual, 1 explicit
     int diag_free = 0;        // diagonal gates never force a SWAP
     int pin_low = -1;         // low memory bits kept in every block (-1 = auto)
-    int fuse_k = 1;           // fusion width (1 = off)
+    int fuse_k = 1;           // 0: one op per gate; 1: diagonal runs combined,
+                              // Hadamard normalization deferred
 };
 
 struct PlanStats {
@@ -98,7 +142,7 @@ struct PlanStats {
 struct Plan {
     std::vector<Step> steps;
     std::vector<K2Op> ops;
-    std::vector<double> fused_mats;  // 2^k x 2^k complex, row-major (re, im)
+    std::vector<uint8_t> table;      // DiagRec, lane/wave tables, UGroup, UTerm
     PlanStats stats;
     std::vector<int> l2p_after;      // layout after the plan
     int l = 0;
@@ -108,20 +152,23 @@ struct Plan {
 int default_block_qubits(int dtype);
 int max_block_qubits(int dtype);
 
-// Build the 2x2 FP64 matrix and class of an sv_gate-like record. Returns
-// false for an unknown op.
+// Build the 2x2 FP64 matrix and class of a gate. Returns false for an
+// unknown op.
 bool gate_matrix(int op, double theta, const double *u_in, double *u_out, int *cls);
 
-// Validate and plan. gates: raw records (op, target, control, target2,
-// theta, u[8]) laid out as sv_gate. l2p: layout at entry (size n), updated
-// copy in plan.l2p_after. Returns "" or an error message.
+// Raw gate record, laid out as sv_gate.
 struct RawGate {
     int32_t op, target, control, target2;
     double theta;
     double u[8];
 };
 std::string validate(int n, const RawGate *gates, size_t m);
+// Validate and plan. l2p: layout at entry (size n); the layout after the plan
+// is plan.l2p_after. Returns "" or an error message.
 std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
                       const std::vector<int> &l2p, Plan &plan);
+
+// Angle in turns -> 64-bit fixed point (mod one turn).
+uint64_t turns_fixed(double turns);
 
 }  // namespace svp

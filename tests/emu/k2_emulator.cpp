@@ -1,0 +1,258 @@
+// Test-only host emulator of the planner's device programs.
+//
+// It runs the steps that make_plan produces (plain sweeps, explicit exchange
+// passes and block-resident passes with their op programs and tables) on a
+// complex<double> state, re-implementing the kernels' index arithmetic
+// (register slots, thread-id deposit, LDS re-layout, lane/wave/block-uniform
+// factors) on the CPU. Tests compare it with the FP64 oracle, so a wrong op
+// or table emitted by the planner is caught without a GPU. It is not linked
+// into the simulator library.
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../paper_2605_15098_amd/csrc/plan.h"
+
+using cd = std::complex<double>;
+using namespace svp;
+
+namespace {
+
+void apply_pair_gate(std::vector<cd> &S, int n, const MGate &g)
+{
+    const uint64_t N = 1ull << n;
+    const cd u00(g.u[0], g.u[1]), u01(g.u[2], g.u[3]), u10(g.u[4], g.u[5]), u11(g.u[6], g.u[7]);
+    for (uint64_t j = 0; j < N; ++j) {
+        if ((j >> g.t) & 1ull) continue;
+        if (g.c >= 0 && !((j >> g.c) & 1ull)) continue;
+        const uint64_t k = j | (1ull << g.t);
+        const cd a = S[j], b = S[k];
+        S[j] = u00 * a + u01 * b;
+        S[k] = u10 * a + u11 * b;
+    }
+}
+
+cd expturn(uint64_t a)
+{
+    const double x = std::ldexp((double)(int64_t)a, -63);
+    return cd(std::cos(M_PI * x), std::sin(M_PI * x));
+}
+
+void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
+{
+    const int l = st.l, r = st.logr, R = 1 << r, tb = l - r;
+    const int NT = 1 << tb;
+    std::vector<int> nb;
+    {
+        std::vector<bool> in(n, false);
+        for (int i = 0; i < l; ++i) in[st.bits[i]] = true;
+        for (int p = 0; p < n; ++p)
+            if (!in[p]) nb.push_back(p);
+    }
+    const uint64_t nblocks = 1ull << (n - l);
+    std::vector<cd> lds(1ull << l);
+    const uint8_t *table = plan.table.data();
+    for (uint64_t bid = 0; bid < nblocks; ++bid) {
+        uint64_t base = 0;
+        for (int i = 0; i < n - l; ++i) base |= ((bid >> i) & 1ull) << nb[i];
+        std::vector<cd> ufac(st.nug);
+        for (int g = 0; g < st.nug; ++g) {
+            const UGroup *ug = reinterpret_cast<const UGroup *>(table + st.ug_off) + g;
+            const UTerm *tm = reinterpret_cast<const UTerm *>(table + ug->term_off);
+            uint64_t acc = 0;
+            for (int j = 0; j < ug->nterms; ++j)
+                if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
+            ufac[g] = expturn(acc);
+        }
+        // per-thread registers; canonical layout: slot 0 = local bit 0,
+        // slots 1.. = top local bits
+        std::vector<std::vector<cd>> a(NT, std::vector<cd>(R));
+        std::vector<int> rb(r);
+        rb[0] = 0;
+        for (int j = 1; j < r; ++j) rb[j] = tb + j;
+        std::vector<uint32_t> tloc(NT);
+        auto set_layout = [&]() {
+            uint32_t rmask = 0;
+            for (int j = 0; j < r; ++j) rmask |= 1u << rb[j];
+            for (int tid = 0; tid < NT; ++tid) {
+                uint32_t tl = 0;
+                int cnt = 0;
+                for (int i = 0; i < l; ++i) {
+                    if ((rmask >> i) & 1u) continue;
+                    tl |= ((uint32_t)(tid >> cnt) & 1u) << i;
+                    ++cnt;
+                }
+                tloc[tid] = tl;
+            }
+        };
+        set_layout();
+        auto code_bit = [&](int tid, int code) {
+            return code >= 64 ? (bool)((base >> (code - 64)) & 1ull) : (bool)((tloc[tid] >> code) & 1u);
+        };
+        auto tpred_of = [&](int tid, const K2Op &op) {
+            return ((tloc[tid] & (uint32_t)op.m0) == (uint32_t)op.m0) && ((base & op.m1) == op.m1);
+        };
+        auto amp_mem = [&](int tid, int k) {
+            uint32_t x = tloc[tid];
+            for (int j = 0; j < r; ++j)
+                if ((k >> j) & 1) x |= 1u << rb[j];
+            uint64_t addr = base;
+            for (int i = 0; i < l; ++i)
+                if ((x >> i) & 1u) addr |= 1ull << st.bits[i];
+            return addr;
+        };
+        auto amp_loc = [&](int tid, int k) {
+            uint32_t x = tloc[tid];
+            for (int j = 0; j < r; ++j)
+                if ((k >> j) & 1) x |= 1u << rb[j];
+            return x;
+        };
+        for (int tid = 0; tid < NT; ++tid)
+            for (int k = 0; k < R; ++k) a[tid][k] = S[amp_mem(tid, k)];
+        for (int oi = 0; oi < st.op_count; ++oi) {
+            const K2Op &op = plan.ops[st.op_begin + oi];
+            if (op.kind == K2_LAYOUT) {
+                for (int tid = 0; tid < NT; ++tid)
+                    for (int k = 0; k < R; ++k) lds[amp_loc(tid, k)] = a[tid][k];
+                for (int j = 0; j < r; ++j) rb[j] = (op.a >> (5 * j)) & 31;
+                set_layout();
+                for (int tid = 0; tid < NT; ++tid)
+                    for (int k = 0; k < R; ++k) a[tid][k] = lds[amp_loc(tid, k)];
+            } else if (op.kind == K2_PHASE) {
+                const cd z(op.v[0], op.v[1]);
+                for (int tid = 0; tid < NT; ++tid) {
+                    if (!tpred_of(tid, op)) continue;
+                    for (int k = 0; k < R; ++k)
+                        if ((k & op.a) == op.a) a[tid][k] *= z;
+                }
+            } else if (op.kind == K2_DIAG) {
+                const cd d0(op.v[0], op.v[1]), d1(op.v[2], op.v[3]);
+                for (int tid = 0; tid < NT; ++tid) {
+                    if (!tpred_of(tid, op)) continue;
+                    for (int k = 0; k < R; ++k) {
+                        if ((k & op.c) != op.c) continue;
+                        bool sel = op.a >= 0 ? (bool)((k >> op.a) & 1) : code_bit(tid, op.b);
+                        a[tid][k] *= sel ? d1 : d0;
+                    }
+                }
+            } else if (op.kind == K2_DIAGRUN) {
+                const DiagRec *rec = reinterpret_cast<const DiagRec *>(table + op.a);
+                const double *qt = reinterpret_cast<const double *>(rec + 1);
+                for (int tid = 0; tid < NT; ++tid) {
+                    std::vector<cd> f(rec->ngroups, cd(1, 0));
+                    for (int g = 0; g < rec->ngroups; ++g) {
+                        const DiagGroup &G = rec->g[g];
+                        bool on = true;
+                        if (G.cond_kind == 1) on = (base >> G.cond_bit) & 1ull;
+                        else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1;
+                        if (!on) continue;
+                        cd v(1, 0);
+                        if (G.uidx >= 0) v = ufac[G.uidx];
+                        if (G.wave_off >= 0) {
+                            const double *w = reinterpret_cast<const double *>(table + G.wave_off);
+                            v *= cd(w[2 * (tid >> 6)], w[2 * (tid >> 6) + 1]);
+                        }
+                        if (G.lane_off >= 0) {
+                            const double *w = reinterpret_cast<const double *>(table + G.lane_off);
+                            v *= cd(w[2 * (tid & 63)], w[2 * (tid & 63) + 1]);
+                        }
+                        f[g] = v;
+                    }
+                    for (int k = 0; k < R; ++k) {
+                        if (!((rec->kmask >> k) & 1ull)) continue;
+                        cd F(qt[2 * k], qt[2 * k + 1]);
+                        for (int g = 0; g < rec->ngroups; ++g)
+                            if ((rec->g[g].rmask & k) == rec->g[g].rmask) F *= f[g];
+                        a[tid][k] *= F;
+                    }
+                }
+            } else if (op.kind == K2_SCALE) {
+                for (int tid = 0; tid < NT; ++tid)
+                    for (int k = 0; k < R; ++k) a[tid][k] *= op.v[0];
+            } else {
+                const int J = op.a, H = 1 << J;
+                const cd u00(op.v[0], op.v[1]), u01(op.v[2], op.v[3]), u10(op.v[4], op.v[5]),
+                    u11(op.v[6], op.v[7]);
+                for (int tid = 0; tid < NT; ++tid) {
+                    const bool tpred = op.b == CK_MEM ? code_bit(tid, op.c) : true;
+                    if (!tpred) continue;
+                    for (int k = 0; k < R; ++k) {
+                        if (k & H) continue;
+                        if (op.b == CK_SLOT && !((k >> op.c) & 1)) continue;
+                        cd x = a[tid][k], y = a[tid][k + H];
+                        if (op.kind == K2_H) {
+                            const double s = 0.70710678118654752440;
+                            a[tid][k] = (x + y) * s;
+                            a[tid][k + H] = (x - y) * s;
+                        } else if (op.kind == K2_HU) {
+                            a[tid][k] = x + y;
+                            a[tid][k + H] = x - y;
+                        } else if (op.kind == K2_X) {
+                            a[tid][k] = y;
+                            a[tid][k + H] = x;
+                        } else {
+                            a[tid][k] = u00 * x + u01 * y;
+                            a[tid][k + H] = u10 * x + u11 * y;
+                        }
+                    }
+                }
+            }
+        }
+        for (int tid = 0; tid < NT; ++tid)
+            for (int k = 0; k < R; ++k) S[amp_mem(tid, k)] = a[tid][k];
+    }
+}
+
+}  // namespace
+
+extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy, int remap, int diag_free,
+                         int pin_low, int fuse_k, const void *gates, size_t m, double *state_inout,
+                         int64_t *counts_out)
+{
+    PlanConfig c;
+    c.n = n;
+    c.dtype = dtype;
+    c.mode = mode;
+    c.l = l;
+    c.logr = logr;
+    c.policy = policy;
+    c.remap = remap;
+    c.diag_free = diag_free;
+    c.pin_low = pin_low;
+    c.fuse_k = fuse_k;
+    std::vector<int> l2p(n);
+    for (int q = 0; q < n; ++q) l2p[q] = q;
+    Plan plan;
+    std::string err = make_plan(c, reinterpret_cast<const RawGate *>(gates), m, l2p, plan);
+    if (!err.empty()) return -1;
+    const uint64_t N = 1ull << n;
+    std::vector<cd> S(N);
+    for (uint64_t i = 0; i < N; ++i) S[i] = cd(state_inout[2 * i], state_inout[2 * i + 1]);
+    for (const Step &st : plan.steps) {
+        if (st.kind == ST_K1) {
+            apply_pair_gate(S, n, st.g);
+        } else if (st.kind == ST_K3) {
+            for (uint64_t i = 0; i < N; ++i) {
+                if (((i >> st.p) & 1ull) && !((i >> st.v) & 1ull)) {
+                    const uint64_t k = i ^ (1ull << st.p) ^ (1ull << st.v);
+                    std::swap(S[i], S[k]);
+                }
+            }
+        } else {
+            run_k2(S, n, st, plan);
+        }
+    }
+    for (uint64_t x = 0; x < N; ++x) {
+        uint64_t p = 0;
+        for (int q = 0; q < n; ++q) p |= ((x >> q) & 1ull) << plan.l2p_after[q];
+        state_inout[2 * x] = S[p].real();
+        state_inout[2 * x + 1] = S[p].imag();
+    }
+    counts_out[0] = plan.stats.passes;
+    counts_out[1] = plan.stats.swaps;
+    counts_out[2] = (int64_t)plan.ops.size();
+    counts_out[3] = (int64_t)plan.table.size();
+    return 0;
+}

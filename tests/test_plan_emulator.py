@@ -1,0 +1,123 @@
+"""The planner's device programs, run by a host emulator, against the oracle.
+
+tests/emu/k2_emulator.cpp re-implements the block-pass kernel's semantics
+(register slots, lane/wave thread-id bits, LDS re-layouts, diagonal-run
+tables, block-uniform factors, deferred Hadamard scaling) on the CPU in FP64.
+Every schedule the planner can emit is checked here without a GPU; the GPU
+tests then check the kernels against the same oracle.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import qpe as cf
+from paper_2605_15098_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = [os.path.join(HERE, "emu", "k2_emulator.cpp"),
+       os.path.join(ROOT, "paper_2605_15098_amd", "csrc", "plan.cpp")]
+LIB = os.path.join(HERE, "emu", "libk2emu.so")
+_lib = None
+
+
+def emu():
+    global _lib
+    if _lib is None:
+        newest = max(os.path.getmtime(p) for p in SRC + [SRC[1].replace(".cpp", ".h")])
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
+            tmp = LIB + f".tmp{os.getpid()}"
+            subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp] + SRC, check=True)
+            os.replace(tmp, LIB)
+        lib = ctypes.CDLL(LIB)
+        lib.emu_apply.argtypes = [ctypes.c_int] * 10 + [ctypes.c_void_p, ctypes.c_size_t,
+                                                        ctypes.POINTER(ctypes.c_double),
+                                                        ctypes.POINTER(ctypes.c_int64)]
+        lib.emu_apply.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def run(n, gates, state=None, dtype=0, mode=1, l=0, logr=4, policy=1, remap=0, diag_free=1,
+        pin=-1, fuse=1):
+    s = oracle.zero_state(n) if state is None else np.array(state, dtype=np.complex128)
+    counts = (ctypes.c_int64 * 4)()
+    g = np.ascontiguousarray(gates)
+    rc = emu().emu_apply(n, dtype, mode, l, logr, policy, remap, diag_free, pin, fuse,
+                         g.ctypes.data if len(g) else None, len(g),
+                         s.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), counts)
+    assert rc == 0
+    return s, list(counts)
+
+
+CONFIGS = [
+    dict(),                                          # default: look-ahead bulk remap, combined diagonals
+    dict(fuse=0),                                    # one op per gate
+    dict(policy=0, diag_free=0),                     # LRU, virtual
+    dict(policy=0, remap=1, diag_free=0),            # the paper's schedule
+    dict(policy=1, remap=1),                         # explicit look-ahead
+    dict(logr=2), dict(logr=3), dict(logr=5),
+    dict(pin=0), dict(pin=5),
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: ",".join(f"{k}={v}" for k, v in c.items()) or "default")
+@pytest.mark.parametrize("n,l", [(3, 3), (6, 4), (9, 7), (11, 8), (12, 10)])
+def test_random_circuit_programs(n, l, cfg):
+    if cfg.get("logr", 4) > l:
+        pytest.skip("fewer local bits than register bits")
+    rng = np.random.default_rng(n * 100 + l)
+    g = W.random_mixed_circuit(n, 90, rng)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    want = oracle.apply(n, g, psi0)
+    got, _ = run(n, g, psi0, l=l, **cfg)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+@pytest.mark.parametrize("cfg", CONFIGS[:5], ids=lambda c: ",".join(f"{k}={v}" for k, v in c.items()) or "default")
+@pytest.mark.parametrize("n,l,dtype", [(10, 6, 0), (13, 8, 1), (14, 10, 0)])
+def test_qpe_programs(n, l, dtype, cfg):
+    phi = W.phi_for_seed(n)
+    g = W.qpe_gates(n, phi)
+    got, counts = run(n, g, dtype=dtype, l=l, **cfg)
+    assert np.max(np.abs(got - cf.qpe_state(n, phi))) < 1e-12
+
+
+def test_diagonal_dense_runs_many_groups():
+    """Long runs of controlled phases between all bit classes (register,
+    lane, wave, block-uniform) force several factor groups per run."""
+    n = 13
+    rng = np.random.default_rng(3)
+    rows = []
+    for _ in range(6):
+        for _ in range(40):
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            kind = rng.integers(0, 4)
+            th = float(rng.random() * 6.28)
+            rows.append([("P", b, a, th), ("Z", b, a, 0.0), ("RZ", b, a, th), ("RZ", a, -1, th)][kind])
+        rows += [("H", int(q), -1, 0.0) for q in rng.choice(n, 3, replace=False)]
+    g = W.gates_from_tuples(rows)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    want = oracle.apply(n, g, psi0)
+    for cfg in (dict(l=9), dict(l=11, logr=5), dict(l=6, logr=2), dict(l=9, fuse=0)):
+        got, _ = run(n, g, psi0, **cfg)
+        assert np.max(np.abs(got - want)) < 1e-12, cfg
+
+
+def test_non_unit_diagonal_u2():
+    n = 8
+    rng = np.random.default_rng(4)
+    g = W.random_mixed_circuit(n, 40, rng, with_u2=False)
+    d = W.gates_from_tuples([("U2", 3, 5, 0.0), ("U2", 6, -1, 0.0)])
+    d[0]["u"] = [0.5, 0.1, 0, 0, 0, 0, 2.0, -0.3]
+    d[1]["u"] = [0.0, 1.0, 0, 0, 0, 0, -1.0, 0.0]
+    g = np.concatenate([g[:20], d, g[20:]])
+    want = oracle.apply(n, g)
+    got, _ = run(n, g, l=6)
+    assert np.max(np.abs(got - want)) < 1e-12
