@@ -317,6 +317,21 @@ __device__ __forceinline__ void k2_pairs(C *a, int kind, const double *v, bool t
 // 16-byte access.
 // Largest work-group of a block-pass variant: big register tiles need the
 // VGPR budget of fewer waves per SIMD.
+// Unnormalized Hadamard on register slot J: (a, b) -> (a + b, a - b).
+template <int J, int R, typename C> __device__ __forceinline__ void k2_hu(C *a)
+{
+    constexpr int H = 1 << J;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (k & H) continue;
+        const C x = a[k], y = a[k + H];
+        a[k].x = x.x + y.x;
+        a[k].y = x.y + y.y;
+        a[k + H].x = x.x - y.x;
+        a[k + H].y = x.y - y.y;
+    }
+}
+
 template <typename T, int LOGR> constexpr int k2_max_threads()
 {
     return (LOGR + (sizeof(T) == 8 ? 1 : 0)) >= 5 ? (LOGR + (sizeof(T) == 8 ? 1 : 0) >= 6 ? 256 : 512) : 1024;
@@ -396,7 +411,50 @@ k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ op
     for (int oi = 0; oi < args.nops; ++oi) {
         const svp::K2Op &op = ops[oi];
         const int kind = op.kind;
-        if (kind == svp::K2_LAYOUT) {
+        if (kind == svp::K2_HU) {
+            // uncontrolled Hadamard without the 1/sqrt2 (applied once per pass)
+            switch (op.a) {
+            case 0: k2_hu<0, R>(a); break;
+            case 1: if constexpr (LOGR > 1) k2_hu<1, R>(a); break;
+            case 2: if constexpr (LOGR > 2) k2_hu<2, R>(a); break;
+            case 3: if constexpr (LOGR > 3) k2_hu<3, R>(a); break;
+            case 4: if constexpr (LOGR > 4) k2_hu<4, R>(a); break;
+            default: break;
+            }
+        } else if (kind == svp::K2_DIAGRUN) {
+            // one phase multiply per amplitude for a run of diagonal gates:
+            // slot k in kmask gets Q[k] (k in qmask) times the thread factor
+            // U[uidx] * wave_table[wave] * lane_table[lane], all in FP64 and
+            // rounded once
+            const svp::DiagRec *rec = reinterpret_cast<const svp::DiagRec *>(args.table + op.a);
+            const double2 *qt = reinterpret_cast<const double2 *>(rec + 1);
+            const uint32_t kmask = rec->kmask, qmask = rec->qmask;
+            double2 f = make_double2(1.0, 0.0);
+            if (rec->has_group) {
+                const svp::DiagGroup &G = rec->g;
+                bool on = true;
+                if (G.cond_kind == 1) on = (base >> G.cond_bit) & 1ull;
+                else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1u;
+                if (on) {
+                    if (G.uidx >= 0) f = ufac[G.uidx];
+                    if (G.wave_off >= 0)
+                        f = cmul(f, reinterpret_cast<const double2 *>(args.table + G.wave_off)[tid >> 6]);
+                    if (G.lane_off >= 0)
+                        f = cmul(f, reinterpret_cast<const double2 *>(args.table + G.lane_off)[tid & 63u]);
+                }
+            }
+            const C fc = mk<C>(f.x, f.y);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (!((kmask >> k) & 1u)) continue;
+                C Fk = fc;
+                if ((qmask >> k) & 1u) {
+                    const double2 F = cmul(qt[k], f);
+                    Fk = mk<C>(F.x, F.y);
+                }
+                a[k] = cmul(Fk, a[k]);
+            }
+        } else if (kind == svp::K2_LAYOUT) {
             {
                 const uint32_t tsw = swz<C>(tloc) * (uint32_t)sizeof(C);
 #pragma unroll
@@ -428,42 +486,6 @@ k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ op
                 }
             }
             __syncthreads();
-        } else if (kind == svp::K2_DIAGRUN) {
-            // one phase multiply per amplitude for a whole run of diagonal
-            // gates: F(k) = Q[k] * prod of the thread factors whose slot mask
-            // k covers; factors assembled in FP64, rounded once
-            const svp::DiagRec *rec = reinterpret_cast<const svp::DiagRec *>(args.table + op.a);
-            const double2 *qt = reinterpret_cast<const double2 *>(rec + 1);
-            const int ng = rec->ngroups;
-            const uint64_t kmask = rec->kmask;
-            double2 f[svp::DIAG_MAX_GROUPS];
-            int rm[svp::DIAG_MAX_GROUPS];
-#pragma unroll
-            for (int g = 0; g < svp::DIAG_MAX_GROUPS; ++g) {
-                f[g] = make_double2(1.0, 0.0);
-                rm[g] = 0;
-                if (g >= ng) continue;
-                const svp::DiagGroup &G = rec->g[g];
-                rm[g] = G.rmask;
-                bool on = true;
-                if (G.cond_kind == 1) on = (base >> G.cond_bit) & 1ull;
-                else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1u;
-                if (!on) continue;
-                double2 v = make_double2(1.0, 0.0);  // groups off by condition keep 1
-                if (G.uidx >= 0) v = ufac[G.uidx];
-                if (G.wave_off >= 0) v = cmul(v, reinterpret_cast<const double2 *>(args.table + G.wave_off)[tid >> 6]);
-                if (G.lane_off >= 0) v = cmul(v, reinterpret_cast<const double2 *>(args.table + G.lane_off)[tid & 63u]);
-                f[g] = v;
-            }
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                if (!((kmask >> k) & 1ull)) continue;
-                double2 F = qt[k];
-#pragma unroll
-                for (int g = 0; g < svp::DIAG_MAX_GROUPS; ++g)
-                    if (g < ng && (rm[g] & k) == rm[g]) F = cmul(F, f[g]);
-                a[k] = cmul(mk<C>(F.x, F.y), a[k]);
-            }
         } else if (kind == svp::K2_SCALE) {
             const T sc = (T)op.v[0];
 #pragma unroll
@@ -493,9 +515,7 @@ k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ op
                 }
             } else {
                 const bool sel = code_bit(tloc, base, op.b);
-                C d;
-                d.x = sel ? d1.x : d0.x;
-                d.y = sel ? d1.y : d0.y;
+                const C d = csel(sel, d1, d0);
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     if ((k & rmask) != rmask) continue;

@@ -268,50 +268,59 @@ struct Builder {
             }
             return table_put(tab.data(), tab.size() * sizeof(double));
         };
-        size_t gi = 0;
-        bool first = true;
-        while (first || gi < groups.size()) {
+        // One op per factor group; constant factors ride with the first op
+        // whose group covers their slots, the rest get an op of their own.
+        const uint32_t all = (uint32_t)((1ull << qang.size()) - 1ull);
+        auto cover = [&](int rmask) {
+            uint32_t m = 0;
+            for (size_t k = 0; k < qang.size(); ++k)
+                if ((int(k) & rmask) == rmask) m |= 1u << k;
+            return m;
+        };
+        uint32_t qpend = 0;
+        for (size_t k = 0; k < qang.size(); ++k)
+            if (qang[k] != 0) qpend |= 1u << k;
+        std::vector<double> q(2 * qang.size());
+        for (size_t k = 0; k < qang.size(); ++k) cexp(qang[k], &q[2 * k]);
+        auto put = [&](const DiagRec &rec) {
+            std::vector<uint8_t> blob(sizeof(DiagRec) + q.size() * sizeof(double));
+            std::memcpy(blob.data(), &rec, sizeof(DiagRec));
+            std::memcpy(blob.data() + sizeof(DiagRec), q.data(), q.size() * sizeof(double));
+            K2Op op{};
+            op.kind = K2_DIAGRUN;
+            op.a = table_put(blob.data(), blob.size());
+            plan.ops.push_back(op);
+        };
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            GroupAcc &G = groups[gi];
             DiagRec rec{};
-            const size_t take = std::min<size_t>(DIAG_MAX_GROUPS, groups.size() - gi);
-            rec.ngroups = (int)take;
-            std::vector<double> q(2 * qang.size());
-            for (size_t k = 0; k < qang.size(); ++k) {
-                const uint64_t a = first ? qang[k] : 0;
-                cexp(a, &q[2 * k]);
-                if (a != 0) rec.kmask |= 1ull << k;
+            rec.has_group = 1;
+            rec.kmask = cover(G.rmask) & all;
+            rec.qmask = rec.kmask & qpend;
+            qpend &= ~rec.qmask;
+            DiagGroup &d = rec.g;
+            d.rmask = G.rmask;
+            d.cond_kind = G.cond_kind;
+            d.cond_bit = G.cond_bit;
+            d.uidx = -1;
+            d.lane_off = -1;
+            d.wave_off = -1;
+            if (!G.lane.empty()) d.lane_off = build_table(G.lane, 0, std::min(6, nthread_bits));
+            if (!G.wave.empty()) d.wave_off = build_table(G.wave, 6, nwave_bits);
+            if (!G.glob.empty()) {
+                UGroup ug{(int)uterms.size(), (int)G.glob.size()};
+                for (auto &pr : G.glob) uterms.push_back(UTerm{pr.first, pr.second});
+                d.uidx = (int)ugroups.size();
+                ugroups.push_back(ug);
             }
-            for (size_t j = 0; j < take; ++j) {
-                GroupAcc &G = groups[gi + j];
-                DiagGroup &d = rec.g[j];
-                d.rmask = G.rmask;
-                d.cond_kind = G.cond_kind;
-                d.cond_bit = G.cond_bit;
-                d.uidx = -1;
-                d.lane_off = -1;
-                d.wave_off = -1;
-                if (!G.lane.empty()) d.lane_off = build_table(G.lane, 0, std::min(6, nthread_bits));
-                if (!G.wave.empty()) d.wave_off = build_table(G.wave, 6, nwave_bits);
-                if (!G.glob.empty()) {
-                    UGroup ug{(int)uterms.size(), (int)G.glob.size()};
-                    for (auto &pr : G.glob) uterms.push_back(UTerm{pr.first, pr.second});
-                    d.uidx = (int)ugroups.size();
-                    ugroups.push_back(ug);
-                }
-                for (size_t k = 0; k < qang.size(); ++k)
-                    if ((int(k) & G.rmask) == G.rmask) rec.kmask |= 1ull << k;
-            }
-            if (rec.kmask != 0) {
-                std::vector<uint8_t> blob(sizeof(DiagRec) + q.size() * sizeof(double));
-                std::memcpy(blob.data(), &rec, sizeof(DiagRec));
-                std::memcpy(blob.data() + sizeof(DiagRec), q.data(), q.size() * sizeof(double));
-                K2Op op{};
-                op.kind = K2_DIAGRUN;
-                op.a = table_put(blob.data(), blob.size());
-                op.b = (int)take;
-                plan.ops.push_back(op);
-            }
-            gi += take;
-            first = false;
+            put(rec);
+        }
+        if (qpend != 0) {
+            DiagRec rec{};
+            rec.has_group = 0;
+            rec.kmask = qpend;
+            rec.qmask = qpend;
+            put(rec);
         }
     }
 

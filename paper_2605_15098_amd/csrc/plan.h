@@ -80,16 +80,18 @@ struct DiagGroup {
 };
 static_assert(sizeof(DiagGroup) == 32, "DiagGroup layout");
 
-constexpr int DIAG_MAX_GROUPS = 4;
-// A diagonal run; followed in the table by 2^r complex doubles: the constant
-// factor of each register pattern k.
+// One op of a diagonal run; followed in the table by 2^r complex doubles Q[k]:
+// the constant factor of register pattern k. Amplitude slot k in kmask is
+// multiplied by (k in qmask ? Q[k] : 1) * (has_group ? group factor : 1).
+// The planner guarantees that a group covers every slot in kmask.
 struct DiagRec {
-    uint64_t kmask;     // bit k: amplitude slot k needs a multiply
-    int32_t ngroups;
+    uint32_t kmask;
+    uint32_t qmask;
+    int32_t has_group;
     int32_t pad;
-    DiagGroup g[DIAG_MAX_GROUPS];
+    DiagGroup g;
 };
-static_assert(sizeof(DiagRec) == 144, "DiagRec layout");
+static_assert(sizeof(DiagRec) == 48, "DiagRec layout");
 
 // Block-uniform factor: e^{2 pi i sum angle_j [base covers tmask_j]} with
 // angles as 64-bit fixed-point turns; computed once per work-group.

@@ -40,6 +40,8 @@ cd expturn(uint64_t a)
     return cd(std::cos(M_PI * x), std::sin(M_PI * x));
 }
 
+bool return_error = false;
+
 void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
 {
     const int l = st.l, r = st.logr, R = 1 << r, tb = l - r;
@@ -141,30 +143,31 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
                 const DiagRec *rec = reinterpret_cast<const DiagRec *>(table + op.a);
                 const double *qt = reinterpret_cast<const double *>(rec + 1);
                 for (int tid = 0; tid < NT; ++tid) {
-                    std::vector<cd> f(rec->ngroups, cd(1, 0));
-                    for (int g = 0; g < rec->ngroups; ++g) {
-                        const DiagGroup &G = rec->g[g];
+                    cd f(1, 0);
+                    if (rec->has_group) {
+                        const DiagGroup &G = rec->g;
                         bool on = true;
                         if (G.cond_kind == 1) on = (base >> G.cond_bit) & 1ull;
                         else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1;
-                        if (!on) continue;
-                        cd v(1, 0);
-                        if (G.uidx >= 0) v = ufac[G.uidx];
-                        if (G.wave_off >= 0) {
-                            const double *w = reinterpret_cast<const double *>(table + G.wave_off);
-                            v *= cd(w[2 * (tid >> 6)], w[2 * (tid >> 6) + 1]);
+                        if (on) {
+                            if (G.uidx >= 0) f = ufac[G.uidx];
+                            if (G.wave_off >= 0) {
+                                const double *w = reinterpret_cast<const double *>(table + G.wave_off);
+                                f *= cd(w[2 * (tid >> 6)], w[2 * (tid >> 6) + 1]);
+                            }
+                            if (G.lane_off >= 0) {
+                                const double *w = reinterpret_cast<const double *>(table + G.lane_off);
+                                f *= cd(w[2 * (tid & 63)], w[2 * (tid & 63) + 1]);
+                            }
                         }
-                        if (G.lane_off >= 0) {
-                            const double *w = reinterpret_cast<const double *>(table + G.lane_off);
-                            v *= cd(w[2 * (tid & 63)], w[2 * (tid & 63) + 1]);
-                        }
-                        f[g] = v;
+                        // the planner promises the group covers every multiplied slot
+                        for (int k = 0; k < R; ++k)
+                            if (((rec->kmask >> k) & 1u) && (k & G.rmask) != G.rmask) return_error = true;
                     }
                     for (int k = 0; k < R; ++k) {
-                        if (!((rec->kmask >> k) & 1ull)) continue;
-                        cd F(qt[2 * k], qt[2 * k + 1]);
-                        for (int g = 0; g < rec->ngroups; ++g)
-                            if ((rec->g[g].rmask & k) == rec->g[g].rmask) F *= f[g];
+                        if (!((rec->kmask >> k) & 1u)) continue;
+                        cd F = f;
+                        if ((rec->qmask >> k) & 1u) F *= cd(qt[2 * k], qt[2 * k + 1]);
                         a[tid][k] *= F;
                     }
                 }
@@ -225,6 +228,7 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
     std::vector<int> l2p(n);
     for (int q = 0; q < n; ++q) l2p[q] = q;
     Plan plan;
+    return_error = false;
     std::string err = make_plan(c, reinterpret_cast<const RawGate *>(gates), m, l2p, plan);
     if (!err.empty()) return -1;
     const uint64_t N = 1ull << n;
@@ -250,6 +254,7 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
         state_inout[2 * x] = S[p].real();
         state_inout[2 * x + 1] = S[p].imag();
     }
+    if (return_error) return -2;
     counts_out[0] = plan.stats.passes;
     counts_out[1] = plan.stats.swaps;
     counts_out[2] = (int64_t)plan.ops.size();
