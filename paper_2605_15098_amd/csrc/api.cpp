@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/sv.h"
+#include "jit.h"
 #include "launch.h"
 #include "plan.h"
 
@@ -258,6 +259,20 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
         }
         SV_HIP(hipMemcpyAsync(h->dtab, plan.table.data(), need, hipMemcpyHostToDevice, h->stream), "table upload");
     }
+    // Block passes run as kernels compiled for their op lists (cached), unless
+    // SV_JIT=0 selects the op interpreter. Compilation happens before the
+    // first event so device time covers only the kernels.
+    const char *jenv = std::getenv("SV_JIT");
+    const bool use_jit = !(jenv && jenv[0] == '0');
+    std::vector<const void *> jit(plan.steps.size(), nullptr);
+    if (use_jit) {
+        for (size_t i = 0; i < plan.steps.size(); ++i) {
+            if (plan.steps[i].kind != svp::ST_K2) continue;
+            std::string err;
+            hipError_t e = svj::prepare(plan.steps[i], plan, h->dtype, &jit[i], &err);
+            if (e != hipSuccess) return fail(SV_ERR_DEVICE, err.empty() ? std::string("pass compilation: ") + hipGetErrorString(e) : err);
+        }
+    }
     h->kev_kind.clear();
     if (h->kernel_timing) {
         const size_t need = 2 * plan.steps.size();
@@ -268,7 +283,8 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
         }
     }
     SV_HIP(hipEventRecord(h->ev0, h->stream), "hipEventRecord");
-    for (const svp::Step &s : plan.steps) {
+    for (size_t si = 0; si < plan.steps.size(); ++si) {
+        const svp::Step &s = plan.steps[si];
         if (launch_fault()) return fail(SV_ERR_DEVICE, "injected launch failure");
         hipError_t e = hipSuccess;
         if (h->kernel_timing) {
@@ -295,7 +311,8 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
             int k = 0;
             for (int p = 0; p < h->n; ++p)
                 if (!in[p]) a.nbits[k++] = (int8_t)p;
-            e = svk::k2_pass(h->buf, h->n, h->dtype, s.logr, a, h->dops + s.op_begin, h->stream);
+            if (jit[si]) e = svj::launch(jit[si], h->buf, a, h->stream);
+            else e = svk::k2_pass(h->buf, h->n, h->dtype, s.logr, a, h->dops + s.op_begin, h->stream);
         }
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         if (h->kernel_timing) {

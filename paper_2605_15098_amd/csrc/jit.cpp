@@ -1,0 +1,231 @@
+// Pass kernels generated at run time.
+//
+// A block pass's op list is known once the planner has run, so instead of
+// interpreting it on every block, the library writes it out as straight-line
+// device code (register slots, masks, tables and constants all fixed),
+// compiles it for gfx950 with hipRTC and launches it through the module API.
+// The generated code calls the same handlers as the interpreter
+// (k2_device.h), in the same order with the same operands, so both produce
+// the same bits. Compiled kernels are cached by their source text.
+#include "jit.h"
+
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+#include "jit_src.inc"  // kJitAbiH, kJitDeviceH: text of k2_abi.h and k2_device.h
+
+struct Entry {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int per_cu = 0;
+    unsigned threads = 0;
+};
+
+std::mutex g_mu;
+std::unordered_map<std::string, Entry> g_cache;
+int g_cus = 0;
+
+std::string hexd(double x)
+{
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%a", x);
+    return buf;
+}
+
+std::string u64s(uint64_t x) { return std::to_string(x) + "ull"; }
+
+}  // namespace
+
+namespace svj {
+
+std::string generate(const svp::Step &s, const svp::Plan &plan, int dtype)
+{
+    const int r = s.logr, l = s.l;
+    const int R = 1 << r;
+    std::ostringstream o;
+    o << "#include \"k2_device.h\"\nusing namespace svk;\n";
+    o << "struct Prog {\n  template <typename T, int LOGR>\n"
+         "  __device__ __forceinline__ void run(typename CT<T>::type *a, K2Ctx &cx) const {\n"
+         "    using C = typename CT<T>::type;\n    constexpr int R = 1 << LOGR;\n    (void)R;\n";
+    std::vector<int> rb(r);
+    rb[0] = 0;
+    for (int j = 1; j < r; ++j) rb[j] = l - r + j;
+    for (int i = 0; i < s.op_count; ++i) {
+        const svp::K2Op &op = plan.ops[s.op_begin + i];
+        switch (op.kind) {
+        case svp::K2_HU:
+            o << "    k2_hu<" << op.a << ", R>(a);\n";
+            break;
+        case svp::K2_LAYOUT: {
+            std::vector<int> nrb(r);
+            for (int j = 0; j < r; ++j) nrb[j] = (op.a >> (5 * j)) & 31;
+            o << "    { const int ro[" << r << "] = {";
+            for (int j = 0; j < r; ++j) o << (j ? ", " : "") << rb[j];
+            o << "}; const int rn[" << r << "] = {";
+            for (int j = 0; j < r; ++j) o << (j ? ", " : "") << nrb[j];
+            o << "}; k2_layout<LOGR>(a, cx, ro, rn); }\n";
+            rb = nrb;
+            break;
+        }
+        case svp::K2_DIAGRUN: {
+            const svp::DiagRec *rec = reinterpret_cast<const svp::DiagRec *>(plan.table.data() + op.a);
+            const double *qt = reinterpret_cast<const double *>(rec + 1);
+            o << "    {\n      double2 f = make_double2(1.0, 0.0);\n";
+            if (rec->has_group) {
+                const svp::DiagGroup &G = rec->g;
+                o << "      const svp::DiagGroup G{" << G.rmask << ", " << G.cond_kind << ", " << G.cond_bit << ", "
+                  << G.uidx << ", " << G.lane_off << ", " << G.wave_off << ", 0, 0};\n"
+                  << "      f = k2_group_factor(G, cx);\n";
+            }
+            o << "      const C fc = mk<C>(f.x, f.y);\n";
+            for (int k = 0; k < R; ++k) {
+                if (!((rec->kmask >> k) & 1u)) continue;
+                const bool q = (rec->qmask >> k) & 1u;
+                o << "      k2_diag_amp(a[" << k << "], " << (q ? "true" : "false") << ", make_double2("
+                  << hexd(qt[2 * k]) << ", " << hexd(qt[2 * k + 1]) << "), f, fc);\n";
+            }
+            o << "    }\n";
+            break;
+        }
+        case svp::K2_SCALE:
+            o << "    k2_scale<R>(a, " << hexd(op.v[0]) << ");\n";
+            break;
+        case svp::K2_PHASE:
+            o << "    k2_phase<R>(a, cx, " << op.a << ", " << (uint32_t)op.m0 << "u, " << u64s(op.m1) << ", mk<C>("
+              << hexd(op.v[0]) << ", " << hexd(op.v[1]) << "));\n";
+            break;
+        case svp::K2_DIAG:
+            o << "    k2_diag<R>(a, cx, " << op.a << ", " << op.b << ", " << op.c << ", " << (uint32_t)op.m0 << "u, "
+              << u64s(op.m1) << ", mk<C>(" << hexd(op.v[0]) << ", " << hexd(op.v[1]) << "), mk<C>("
+              << hexd(op.v[2]) << ", " << hexd(op.v[3]) << "));\n";
+            break;
+        default: {
+            o << "    { const double v[8] = {";
+            for (int k = 0; k < 8; ++k) o << (k ? ", " : "") << hexd(op.v[k]);
+            o << "}; ";
+            const std::string tpred =
+                op.b == svp::CK_MEM ? "code_bit(cx.tloc, cx.base, " + std::to_string(op.c) + ")" : "true";
+            o << "k2_pairs<" << op.a << ", R>(a, " << op.kind << ", v, " << tpred << ", " << op.b << ", "
+              << (op.b == svp::CK_SLOT ? op.c : 0) << "); }\n";
+            break;
+        }
+        }
+    }
+    o << "  }\n};\n";
+    const char *T = dtype == 0 ? "float" : "double";
+    const unsigned threads = 1u << (l - r);
+    const size_t amp = dtype == 0 ? 8 : 16;
+    const size_t lds = ((amp << l) + (size_t)s.nug * 16 + 15) / 16 * 16;
+    o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") svk2_pass(CT<" << T
+      << ">::type *__restrict__ S, svp::K2Args args) {\n"
+      << "  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[" << (lds > 0 ? lds : 16) << "];\n"
+      << "  k2_body<" << T << ", " << r << ">(S, args, lds_raw, Prog{});\n}\n";
+    return o.str();
+}
+
+static hipError_t compile(const std::string &src, Entry &e, std::string *err)
+{
+    hiprtcProgram prog;
+    const char *headers[] = {kJitAbiH, kJitDeviceH};
+    const char *names[] = {"k2_abi.h", "k2_device.h"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "svk2_pass.hip", 2, headers, names) != HIPRTC_SUCCESS) {
+        if (err) *err = "hiprtcCreateProgram failed";
+        return hipErrorInvalidValue;
+    }
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, 7, opts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        if (err) *err = "pass compilation failed: " + log.substr(0, 2000);
+        hiprtcDestroyProgram(&prog);
+        return hipErrorInvalidImage;
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    std::vector<char> code(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    hipError_t he = hipModuleLoadData(&e.mod, code.data());
+    if (he != hipSuccess) return he;
+    he = hipModuleGetFunction(&e.fn, e.mod, "svk2_pass");
+    return he;
+}
+
+std::string compile_check(const std::string &src)
+{
+    hiprtcProgram prog;
+    const char *headers[] = {kJitAbiH, kJitDeviceH};
+    const char *names[] = {"k2_abi.h", "k2_device.h"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "svk2_pass.hip", 2, headers, names) != HIPRTC_SUCCESS)
+        return "hiprtcCreateProgram failed";
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    std::string out;
+    if (hiprtcCompileProgram(prog, 7, opts) != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        out.assign(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &out[0]);
+        if (out.empty()) out = "compile failed";
+    }
+    hiprtcDestroyProgram(&prog);
+    return out;
+}
+
+hipError_t prepare(const svp::Step &s, const svp::Plan &plan, int dtype, const void **handle, std::string *err)
+{
+    const std::string src = generate(s, plan, dtype);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_cus == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+    }
+    auto it = g_cache.find(src);
+    if (it == g_cache.end()) {
+        Entry e;
+        hipError_t he = compile(src, e, err);
+        if (he != hipSuccess) return he;
+        e.threads = 1u << (s.l - s.logr);
+        he = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&e.per_cu, e.fn, (int)e.threads, 0);
+        if (he != hipSuccess) return he;
+        if (e.per_cu < 1) return hipErrorInvalidConfiguration;
+        it = g_cache.emplace(src, e).first;
+    }
+    *handle = &it->second;
+    return hipSuccess;
+}
+
+hipError_t launch(const void *handle, void *S, const svp::K2Args &a, hipStream_t st)
+{
+    const Entry &e = *static_cast<const Entry *>(handle);
+    const uint64_t blocks = 1ull << (a.n - a.l);
+    uint64_t grid = (uint64_t)e.per_cu * (uint64_t)g_cus;
+    if (grid > blocks) grid = blocks;
+    svp::K2Args args = a;
+    void *params[] = {&S, &args};
+    return hipModuleLaunchKernel(e.fn, (unsigned)grid, 1, 1, e.threads, 1, 1, 0, st, params, nullptr);
+}
+
+size_t cache_size()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_cache.size();
+}
+
+}  // namespace svj

@@ -1,0 +1,94 @@
+// Plain-data records shared by the host planner, the block-pass kernels and
+// the pass kernels generated at run time. Only fixed-width integers and
+// doubles; no library types.
+#pragma once
+
+#if defined(__HIPCC_RTC__)
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::int8_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+using __hip_internal::uint8_t;
+#else
+#include <cstdint>
+#endif
+
+namespace svp {
+
+// Block-pass ops (device program).
+enum K2Kind {
+    K2_LAYOUT = 0,   // a: packed register local bits (5 bits each, ascending)
+    K2_DENSE = 1,    // a: slot; b: control kind; c: control slot or bit code;
+                     // v[0..7]: row-major 2x2 (re, im)
+    K2_H = 2,        // as K2_DENSE, Hadamard
+    K2_X = 3,        // as K2_DENSE, exchange
+    K2_PHASE = 4,    // a: slot mask; m0: local-bit mask; m1: block-base mask;
+                     // v[0..1]: factor
+    K2_DIAG = 5,     // a: target slot or -1; b: target bit code when a < 0;
+                     // c: slot mask; m0/m1 as K2_PHASE; v[0..1] d0, v[2..3] d1
+    K2_DIAGRUN = 6,  // a: byte offset of a DiagRec in the table buffer
+    K2_HU = 7,       // unnormalized Hadamard (a+b, a-b) on slot a, no control
+    K2_SCALE = 8,    // every amplitude times v[0]
+};
+// Control of a dense op: none, a register slot, or a bit code (0..l-1 =
+// local bit tested on the thread's local index, 64 + p = memory bit p of the
+// block base).
+enum CtlKind { CK_NONE = 0, CK_SLOT = 1, CK_MEM = 2 };
+
+struct K2Op {
+    int32_t kind, a, b, c;
+    uint64_t m0, m1;
+    double v[8];
+};
+
+// One thread-dependent factor of a diagonal run: applied to the amplitudes
+// whose register slots cover rmask, when the block-uniform or wave-uniform
+// condition holds. factor = U[uidx] * wave_table[wave] * lane_table[lane].
+struct DiagGroup {
+    int32_t rmask;
+    int32_t cond_kind;  // 0 none, 1 memory bit of the block base, 2 thread-id bit (>= 6)
+    int32_t cond_bit;
+    int32_t uidx;       // block-uniform factor index, -1 none
+    int32_t lane_off;   // byte offset of 64 complex doubles, -1 none
+    int32_t wave_off;   // byte offset of 2^(waves) complex doubles, -1 none
+    int32_t pad0, pad1;
+};
+
+// One op of a diagonal run; followed in the table by 2^r complex doubles Q[k]:
+// the constant factor of register pattern k. Amplitude slot k in kmask is
+// multiplied by (k in qmask ? Q[k] : 1) * (has_group ? group factor : 1).
+// The planner guarantees that a group covers every slot in kmask.
+struct DiagRec {
+    uint32_t kmask;
+    uint32_t qmask;
+    int32_t has_group;
+    int32_t pad;
+    DiagGroup g;
+};
+
+// Block-uniform factor: e^{2 pi i sum angle_j [base covers tmask_j]} with
+// angles as 64-bit fixed-point turns; computed once per block.
+struct UGroup {
+    int32_t term_off;   // byte offset of the UTerm array
+    int32_t nterms;
+};
+struct UTerm {
+    uint64_t tmask;
+    uint64_t angle;
+};
+
+// Arguments of one block pass, passed by value.
+struct K2Args {
+    int32_t n;
+    int32_t l;
+    int32_t nops;
+    int32_t nug;               // block-uniform factor groups
+    const uint8_t *table;      // device copy of the plan's table buffer
+    int32_t ug_off;            // byte offset of the UGroup array
+    int32_t vec2;              // 1: memory bit 0 is local bit 0 (16-byte complex64 pairs)
+    int8_t bits[48];           // memory bit of each local bit, ascending
+    int8_t nbits[48];          // memory bits outside the block, ascending
+};
+
+}  // namespace svp

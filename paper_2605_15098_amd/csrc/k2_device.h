@@ -1,0 +1,507 @@
+// Device code shared by the compiled kernels (kernels.hip) and the pass
+// kernels generated at run time (jit.cpp): complex arithmetic, the block-pass
+// op handlers, the persistent block-pass skeleton and the op interpreter.
+// Every gate's arithmetic lives here once, so the plain sweep, the
+// interpreted block pass and a generated block pass compute the same bits.
+#pragma once
+
+#if !defined(__HIPCC_RTC__)
+#include <hip/hip_runtime.h>
+#endif
+
+#include "k2_abi.h"
+
+namespace svk {
+
+template <typename T> struct CT;
+template <> struct CT<float> { using type = float2; };
+template <> struct CT<double> { using type = double2; };
+
+__device__ __forceinline__ float xfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double xfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename C> __host__ __device__ __forceinline__ C mk(double re, double im)
+{
+    C r;
+    r.x = (decltype(r.x))re;
+    r.y = (decltype(r.y))im;
+    return r;
+}
+
+// z * a
+template <typename C> __device__ __forceinline__ C cmul(C z, C a)
+{
+    C r;
+    r.x = xfma(z.x, a.x, -(z.y * a.y));
+    r.y = xfma(z.x, a.y, z.y * a.x);
+    return r;
+}
+
+// u0 * a + u1 * b
+template <typename C> __device__ __forceinline__ C cmad2(C u0, C a, C u1, C b)
+{
+    C r;
+    r.x = xfma(u0.x, a.x, xfma(-u0.y, a.y, xfma(u1.x, b.x, -(u1.y * b.y))));
+    r.y = xfma(u0.x, a.y, xfma(u0.y, a.x, xfma(u1.x, b.y, u1.y * b.x)));
+    return r;
+}
+
+// Component-wise select (a whole-struct ?: on double2 is lowered through
+// scratch memory).
+template <typename C> __device__ __forceinline__ C csel(bool p, C x, C y)
+{
+    C r;
+    r.x = p ? x.x : y.x;
+    r.y = p ? x.y : y.y;
+    return r;
+}
+
+// Hadamard butterfly: ((a+b)/sqrt2, (a-b)/sqrt2)
+template <typename C> __device__ __forceinline__ void hbfly(C &a, C &b)
+{
+    using T = decltype(a.x);
+    const T s = (T)0.70710678118654752440;
+    C x, y;
+    x.x = (a.x + b.x) * s;
+    x.y = (a.y + b.y) * s;
+    y.x = (a.x - b.x) * s;
+    y.y = (a.y - b.y) * s;
+    a = x;
+    b = y;
+}
+
+__device__ __forceinline__ uint64_t insert0(uint64_t x, int b)
+{
+    const uint64_t lo = x & ((1ull << b) - 1ull);
+    return ((x >> b) << (b + 1)) | lo;
+}
+
+__device__ __forceinline__ uint32_t insert0_32(uint32_t x, int b)
+{
+    return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u));
+}
+
+// LDS index swizzle: the low bits that span one 128-byte bank row are XORed
+// with a fold of the higher bits, so lanes whose local indices differ only in
+// high bits still spread over the banks. The map is linear over GF(2) (shifts,
+// XORs and a constant mask), so for disjoint bit sets
+// swz(a | b) = swz(a) ^ swz(b): a thread swizzles its own bits once and each
+// register slot adds a block-uniform term.
+template <typename C> __host__ __device__ __forceinline__ uint32_t swz(uint32_t x)
+{
+    constexpr int E = (sizeof(C) == 8) ? 4 : 3;  // log2(elements per 128 B)
+    constexpr uint32_t M = (1u << E) - 1u;
+    const uint32_t h = x >> E;
+    return x ^ ((h ^ (h >> E) ^ (h >> (2 * E))) & M);
+}
+
+// A non-register condition bit: 0..l-1 = local bit (tested on the thread's
+// local index), 64 + p = memory bit p outside the block (the block base).
+__device__ __forceinline__ bool code_bit(uint32_t tloc, uint64_t base, int code)
+{
+    return code >= 64 ? (bool)((base >> (code - 64)) & 1ull) : (bool)((tloc >> code) & 1u);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Work-group barrier that waits only for this wave's LDS (and scalar)
+// accesses. Outstanding global loads stay in flight, so the next block,
+// prefetched into registers, keeps streaming across re-layouts.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// ------------------------------------------------------------ op handlers
+
+// Dense, Hadamard or exchange gate on register slot J, optionally controlled
+// by another slot (ckind CK_SLOT) or a per-thread predicate (tpred).
+template <int J, int R, typename C>
+__device__ __forceinline__ void k2_pairs(C *a, int kind, const double *v, bool tpred, int ckind, int cslot)
+{
+    const C u00 = mk<C>(v[0], v[1]), u01 = mk<C>(v[2], v[3]);
+    const C u10 = mk<C>(v[4], v[5]), u11 = mk<C>(v[6], v[7]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (k & (1 << J)) continue;
+        if (ckind == svp::CK_SLOT && !((k >> cslot) & 1)) continue;
+        constexpr int H = 1 << J;
+        C x = a[k], y = a[k + H], nx, ny;
+        if (kind == svp::K2_H) {
+            nx = x;
+            ny = y;
+            hbfly(nx, ny);
+        } else if (kind == svp::K2_X) {
+            nx = y;
+            ny = x;
+        } else {
+            nx = cmad2(u00, x, u01, y);
+            ny = cmad2(u10, x, u11, y);
+        }
+        a[k] = csel(tpred, nx, x);
+        a[k + H] = csel(tpred, ny, y);
+    }
+}
+
+// Unnormalized Hadamard on register slot J: (a, b) -> (a + b, a - b).
+template <int J, int R, typename C> __device__ __forceinline__ void k2_hu(C *a)
+{
+    constexpr int H = 1 << J;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (k & H) continue;
+        const C x = a[k], y = a[k + H];
+        a[k].x = x.x + y.x;
+        a[k].y = x.y + y.y;
+        a[k + H].x = x.x - y.x;
+        a[k + H].y = x.y - y.y;
+    }
+}
+
+// Per-block state a program sees.
+struct K2Ctx {
+    uint32_t tid;
+    uint64_t base;
+    uint32_t tloc;               // local index of the thread's slot-0 amplitude
+    unsigned char *lds;          // block buffer for re-layouts
+    const double2 *ufac;         // block-uniform factors
+    const unsigned char *table;  // plan table
+};
+
+// Re-layout through LDS: the amplitudes leave registers in layout rb_old and
+// come back in layout rb_new (both ascending local-bit lists).
+template <int LOGR, typename C>
+__device__ __forceinline__ void k2_layout(C *a, K2Ctx &cx, const int *rb_old, const int *rb_new)
+{
+    constexpr int R = 1 << LOGR;
+    {
+        const uint32_t tsw = swz<C>(cx.tloc) * (uint32_t)sizeof(C);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint32_t kp = 0;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) kp |= 1u << rb_old[j];
+            *reinterpret_cast<C *>(cx.lds + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C)))) = a[k];
+        }
+    }
+    lds_barrier();
+    uint32_t x = cx.tid;
+#pragma unroll
+    for (int j = 0; j < LOGR; ++j) x = insert0_32(x, rb_new[j]);  // zeros land on register bits
+    cx.tloc = x;
+    {
+        const uint32_t tsw = swz<C>(cx.tloc) * (uint32_t)sizeof(C);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint32_t kp = 0;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) kp |= 1u << rb_new[j];
+            a[k] = *reinterpret_cast<const C *>(cx.lds + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C))));
+        }
+    }
+    lds_barrier();
+}
+
+// Thread factor of a diagonal-run group, FP64.
+__device__ __forceinline__ double2 k2_group_factor(const svp::DiagGroup &G, const K2Ctx &cx)
+{
+    double2 f = make_double2(1.0, 0.0);
+    bool on = true;
+    if (G.cond_kind == 1) on = (cx.base >> G.cond_bit) & 1ull;
+    else if (G.cond_kind == 2) on = (cx.tid >> G.cond_bit) & 1u;
+    if (on) {
+        if (G.uidx >= 0) f = cx.ufac[G.uidx];
+        if (G.wave_off >= 0) f = cmul(f, reinterpret_cast<const double2 *>(cx.table + G.wave_off)[cx.tid >> 6]);
+        if (G.lane_off >= 0) f = cmul(f, reinterpret_cast<const double2 *>(cx.table + G.lane_off)[cx.tid & 63u]);
+    }
+    return f;
+}
+
+// One amplitude of a diagonal run: times f, or times Q[k] * f (FP64, rounded
+// once) when the slot has a constant factor.
+template <typename C>
+__device__ __forceinline__ void k2_diag_amp(C &ak, bool with_q, double2 q, double2 f, C fc)
+{
+    C Fk = fc;
+    if (with_q) {
+        const double2 F = cmul(q, f);
+        Fk = mk<C>(F.x, F.y);
+    }
+    ak = cmul(Fk, ak);
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void k2_diagrun(C *a, const K2Ctx &cx, const svp::DiagRec *rec)
+{
+    const double2 *qt = reinterpret_cast<const double2 *>(rec + 1);
+    const uint32_t kmask = rec->kmask, qmask = rec->qmask;
+    double2 f = make_double2(1.0, 0.0);
+    if (rec->has_group) f = k2_group_factor(rec->g, cx);
+    const C fc = mk<C>(f.x, f.y);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (!((kmask >> k) & 1u)) continue;
+        k2_diag_amp(a[k], ((qmask >> k) & 1u) != 0, qt[k], f, fc);
+    }
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void k2_phase(C *a, const K2Ctx &cx, int rmask, uint32_t lmask, uint64_t gmask, C z)
+{
+    const bool tpred = ((cx.tloc & lmask) == lmask) && ((cx.base & gmask) == gmask);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if ((k & rmask) != rmask) continue;
+        a[k] = csel(tpred, cmul(z, a[k]), a[k]);
+    }
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void k2_diag(C *a, const K2Ctx &cx, int slot, int code, int rmask, uint32_t lmask,
+                                        uint64_t gmask, C d0, C d1)
+{
+    const bool tpred = ((cx.tloc & lmask) == lmask) && ((cx.base & gmask) == gmask);
+    if (slot >= 0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if ((k & rmask) != rmask) continue;
+            const C d = csel(((k >> slot) & 1) != 0, d1, d0);
+            a[k] = csel(tpred, cmul(d, a[k]), a[k]);
+        }
+    } else {
+        const C d = csel(code_bit(cx.tloc, cx.base, code), d1, d0);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if ((k & rmask) != rmask) continue;
+            a[k] = csel(tpred, cmul(d, a[k]), a[k]);
+        }
+    }
+}
+
+template <int R, typename C> __device__ __forceinline__ void k2_scale(C *a, double s)
+{
+    using T = decltype(a[0].x);
+    const T sc = (T)s;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        a[k].x *= sc;
+        a[k].y *= sc;
+    }
+}
+
+// ------------------------------------------------------------ skeleton
+
+template <typename T, int LOGR> constexpr int k2_max_threads()
+{
+    return (LOGR + (sizeof(T) == 8 ? 1 : 0)) >= 5 ? (LOGR + (sizeof(T) == 8 ? 1 : 0) >= 6 ? 256 : 512) : 1024;
+}
+
+// Memory bits outside the block, from the block number (work-group uniform).
+__device__ __forceinline__ uint64_t k2_base(uint64_t bid, const svp::K2Args &args)
+{
+    uint64_t base = 0;
+    for (int i = 0; i < args.n - args.l; ++i) base |= ((bid >> i) & 1ull) << args.nbits[i];
+    return uniform64(base);
+}
+
+template <int LOGR, typename C>
+__device__ __forceinline__ void k2_load(C *a, const C *__restrict__ S, uint64_t tmem, const uint64_t *roff, bool vec2)
+{
+    constexpr int R = 1 << LOGR;
+    if (sizeof(C) == 8 && vec2) {
+        // memory bit 0 is local bit 0 = slot 0: slots k, k+1 are adjacent
+#pragma unroll
+        for (int k = 0; k < R; k += 2) {
+            uint64_t addr = tmem;
+#pragma unroll
+            for (int j = 1; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            const float4 v = *reinterpret_cast<const float4 *>(S + addr);
+            a[k] = mk<C>(v.x, v.y);
+            a[k + 1] = mk<C>(v.z, v.w);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint64_t addr = tmem;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            a[k] = S[addr];
+        }
+    }
+}
+
+template <int LOGR, typename C>
+__device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t tmem, const uint64_t *roff, bool vec2)
+{
+    constexpr int R = 1 << LOGR;
+    if (sizeof(C) == 8 && vec2) {
+#pragma unroll
+        for (int k = 0; k < R; k += 2) {
+            uint64_t addr = tmem;
+#pragma unroll
+            for (int j = 1; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            float4 v;
+            v.x = (float)a[k].x;
+            v.y = (float)a[k].y;
+            v.z = (float)a[k + 1].x;
+            v.w = (float)a[k + 1].y;
+            *reinterpret_cast<float4 *>(S + addr) = v;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint64_t addr = tmem;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) addr += roff[j];
+            S[addr] = a[k];
+        }
+    }
+}
+
+// Block-resident pass, persistent: work-group w handles blocks w, w + G, ...
+// (G = grid size) and loads block i+1 into registers while it runs the
+// program on block i. A block is 2^l amplitudes: local bit i is memory bit
+// args.bits[i]; the other memory bits come from the block number. Each thread
+// holds R = 2^LOGR amplitudes in registers; register slot j stands for local
+// bit rb[j]; the remaining local bits, in ascending order, are the bits of
+// threadIdx. A program starts and ends in the canonical layout: slot 0 =
+// local bit 0, slots 1.. = the top LOGR-1 local bits, so lanes walk
+// consecutive memory and, for complex64, slots 0 and 1 form one 16-byte
+// access. lds must hold 2^l amplitudes followed by args.nug double2.
+template <typename T, int LOGR, class Prog>
+__device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
+                                        unsigned char *lds, const Prog &prog)
+{
+    using C = typename CT<T>::type;
+    constexpr int R = 1 << LOGR;
+    const int l = args.l;
+    const int tb = l - LOGR;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nblocks = 1ull << (args.n - l);
+    const bool vec2 = args.vec2 != 0;
+    double2 *ufac = reinterpret_cast<double2 *>(lds + (sizeof(C) << l));
+
+    // canonical-layout addressing, the same for every block
+    uint64_t tmem_local = 0;
+    for (int i = 0; i < tb; ++i) tmem_local |= (uint64_t)((tid >> i) & 1u) << args.bits[i + 1];
+    uint64_t roff[LOGR];
+    roff[0] = 1ull << args.bits[0];
+#pragma unroll
+    for (int j = 1; j < LOGR; ++j) roff[j] = 1ull << args.bits[tb + j];
+
+    uint64_t bid = blockIdx.x;
+    uint64_t base = k2_base(bid, args);
+    C a[R], b[R];
+    k2_load<LOGR>(a, S, base | tmem_local, roff, vec2);
+
+    for (;;) {
+        const uint64_t next = bid + gridDim.x;
+        const bool has_next = next < nblocks;
+        const uint64_t nbase = has_next ? k2_base(next, args) : 0ull;
+        if (has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
+
+        // Block-uniform phase factors of the diagonal runs: each is
+        // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in
+        // 64-bit fixed-point turns and evaluated once per block.
+        if (args.nug > 0) {
+            const svp::UGroup *ug = reinterpret_cast<const svp::UGroup *>(args.table + args.ug_off);
+            for (int g = threadIdx.x; g < args.nug; g += blockDim.x) {
+                const svp::UTerm *tm = reinterpret_cast<const svp::UTerm *>(args.table + ug[g].term_off);
+                uint64_t acc = 0;
+                for (int j = 0; j < ug[g].nterms; ++j)
+                    if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
+                double sn, cs;
+                sincospi(ldexp((double)(int64_t)acc, -63), &sn, &cs);
+                ufac[g] = make_double2(cs, sn);
+            }
+            lds_barrier();
+        }
+
+        K2Ctx cx{tid, base, tid << 1, lds, ufac, args.table};
+        prog.template run<T, LOGR>(a, cx);
+
+        // the program ends in the canonical layout
+        k2_store<LOGR>(a, S, base | tmem_local, roff, vec2);
+        if (!has_next) break;
+        if (args.nug > 0) lds_barrier();  // the next block's factors overwrite ufac
+#pragma unroll
+        for (int k = 0; k < R; ++k) a[k] = b[k];
+        base = nbase;
+        bid = next;
+    }
+}
+
+// ------------------------------------------------------------ interpreter
+
+// Runs the op list of a pass (ops[0..nops)) on one block.
+struct K2Interp {
+    const svp::K2Op *__restrict__ ops;
+    int nops;
+    int l;
+
+    template <typename T, int LOGR>
+    __device__ __forceinline__ void run(typename CT<T>::type *a, K2Ctx &cx) const
+    {
+        using C = typename CT<T>::type;
+        constexpr int R = 1 << LOGR;
+        int rb[LOGR];
+        rb[0] = 0;
+#pragma unroll
+        for (int j = 1; j < LOGR; ++j) rb[j] = l - LOGR + j;
+        for (int oi = 0; oi < nops; ++oi) {
+            const svp::K2Op &op = ops[oi];
+            const int kind = op.kind;
+            if (kind == svp::K2_HU) {
+                switch (op.a) {
+                case 0: k2_hu<0, R>(a); break;
+                case 1: if constexpr (LOGR > 1) k2_hu<1, R>(a); break;
+                case 2: if constexpr (LOGR > 2) k2_hu<2, R>(a); break;
+                case 3: if constexpr (LOGR > 3) k2_hu<3, R>(a); break;
+                case 4: if constexpr (LOGR > 4) k2_hu<4, R>(a); break;
+                default: break;
+                }
+            } else if (kind == svp::K2_DIAGRUN) {
+                k2_diagrun<R>(a, cx, reinterpret_cast<const svp::DiagRec *>(cx.table + op.a));
+            } else if (kind == svp::K2_LAYOUT) {
+                int nrb[LOGR];
+#pragma unroll
+                for (int j = 0; j < LOGR; ++j) nrb[j] = (op.a >> (5 * j)) & 31;
+                k2_layout<LOGR>(a, cx, rb, nrb);
+#pragma unroll
+                for (int j = 0; j < LOGR; ++j) rb[j] = nrb[j];
+            } else if (kind == svp::K2_SCALE) {
+                k2_scale<R>(a, op.v[0]);
+            } else if (kind == svp::K2_PHASE) {
+                k2_phase<R>(a, cx, op.a, (uint32_t)op.m0, op.m1, mk<C>(op.v[0], op.v[1]));
+            } else if (kind == svp::K2_DIAG) {
+                k2_diag<R>(a, cx, op.a, op.b, op.c, (uint32_t)op.m0, op.m1, mk<C>(op.v[0], op.v[1]),
+                           mk<C>(op.v[2], op.v[3]));
+            } else {
+                const int ckind = op.b;
+                const bool tpred = (ckind == svp::CK_MEM) ? code_bit(cx.tloc, cx.base, op.c) : true;
+                const int cslot = op.c;
+                switch (op.a) {
+                case 0: k2_pairs<0, R>(a, kind, op.v, tpred, ckind, cslot); break;
+                case 1: if constexpr (LOGR > 1) k2_pairs<1, R>(a, kind, op.v, tpred, ckind, cslot); break;
+                case 2: if constexpr (LOGR > 2) k2_pairs<2, R>(a, kind, op.v, tpred, ckind, cslot); break;
+                case 3: if constexpr (LOGR > 3) k2_pairs<3, R>(a, kind, op.v, tpred, ckind, cslot); break;
+                case 4: if constexpr (LOGR > 4) k2_pairs<4, R>(a, kind, op.v, tpred, ckind, cslot); break;
+                default: break;
+                }
+            }
+        }
+    }
+};
+
+}  // namespace svk

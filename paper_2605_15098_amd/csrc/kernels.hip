@@ -15,79 +15,18 @@
 //
 // Complex values are interleaved (re, im): float2 for complex64 and double2
 // for complex128. Gate matrices arrive in binary64 and are rounded once.
-// The single-gate arithmetic (cmul, cmad2, hbfly) is shared by k1 and k2 so
-// an unfused partitioned run reproduces the plain run bit for bit.
+// The single-gate arithmetic (cmul, cmad2, hbfly in k2_device.h) is shared by
+// k1 and k2 so an unfused partitioned run reproduces the plain run bit for
+// bit.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
+#include "k2_device.h"
 #include "launch.h"
 #include "plan.h"
 
 namespace svk {
-
-template <typename T> struct CT;
-template <> struct CT<float> { using type = float2; };
-template <> struct CT<double> { using type = double2; };
-
-__device__ __forceinline__ float xfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double xfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <typename C> __host__ __device__ __forceinline__ C mk(double re, double im)
-{
-    C r;
-    r.x = (decltype(r.x))re;
-    r.y = (decltype(r.y))im;
-    return r;
-}
-
-// z * a
-template <typename C> __device__ __forceinline__ C cmul(C z, C a)
-{
-    C r;
-    r.x = xfma(z.x, a.x, -(z.y * a.y));
-    r.y = xfma(z.x, a.y, z.y * a.x);
-    return r;
-}
-
-// u0 * a + u1 * b
-template <typename C> __device__ __forceinline__ C cmad2(C u0, C a, C u1, C b)
-{
-    C r;
-    r.x = xfma(u0.x, a.x, xfma(-u0.y, a.y, xfma(u1.x, b.x, -(u1.y * b.y))));
-    r.y = xfma(u0.x, a.y, xfma(u0.y, a.x, xfma(u1.x, b.y, u1.y * b.x)));
-    return r;
-}
-
-// Component-wise select (a whole-struct ?: on double2 is lowered through
-// scratch memory).
-template <typename C> __device__ __forceinline__ C csel(bool p, C x, C y)
-{
-    C r;
-    r.x = p ? x.x : y.x;
-    r.y = p ? x.y : y.y;
-    return r;
-}
-
-// Hadamard butterfly: ((a+b)/sqrt2, (a-b)/sqrt2)
-template <typename C> __device__ __forceinline__ void hbfly(C &a, C &b)
-{
-    using T = decltype(a.x);
-    const T s = (T)0.70710678118654752440;
-    C x, y;
-    x.x = (a.x + b.x) * s;
-    x.y = (a.y + b.y) * s;
-    y.x = (a.x - b.x) * s;
-    y.y = (a.y - b.y) * s;
-    a = x;
-    b = y;
-}
-
-__device__ __forceinline__ uint64_t insert0(uint64_t x, int b)
-{
-    const uint64_t lo = x & ((1ull << b) - 1ull);
-    return ((x >> b) << (b + 1)) | lo;
-}
 
 // ---------------------------------------------------------------- init
 
@@ -248,320 +187,14 @@ hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st)
 
 // ---------------------------------------------------------------- k2
 
-// LDS index swizzle: the low bits that span one 128-byte bank row are XORed
-// with a fold of the higher bits, so lanes whose local indices differ only in
-// high bits still spread over the banks. The map is linear over GF(2) (shifts,
-// XORs and a constant mask), so for disjoint bit sets
-// swz(a | b) = swz(a) ^ swz(b): a thread swizzles its own bits once and each
-// register slot adds a block-uniform term.
-template <typename C> __host__ __device__ __forceinline__ uint32_t swz(uint32_t x)
-{
-    constexpr int E = (sizeof(C) == 8) ? 4 : 3;  // log2(elements per 128 B)
-    constexpr uint32_t M = (1u << E) - 1u;
-    const uint32_t h = x >> E;
-    return x ^ ((h ^ (h >> E) ^ (h >> (2 * E))) & M);
-}
-
-__device__ __forceinline__ uint32_t insert0_32(uint32_t x, int b)
-{
-    return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u));
-}
-
-// Non-register condition bits are coded as: 0..l-1 = local bit (tested on the
-// thread's local index), 64 + p = memory bit p outside the block (tested on
-// the block base).
-__device__ __forceinline__ bool code_bit(uint32_t tloc, uint64_t base, int code)
-{
-    return code >= 64 ? (bool)((base >> (code - 64)) & 1ull) : (bool)((tloc >> code) & 1u);
-}
-
-template <int J, int R, typename C>
-__device__ __forceinline__ void k2_pairs(C *a, int kind, const double *v, bool tpred, int ckind, int cslot)
-{
-    const C u00 = mk<C>(v[0], v[1]), u01 = mk<C>(v[2], v[3]);
-    const C u10 = mk<C>(v[4], v[5]), u11 = mk<C>(v[6], v[7]);
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        if (k & (1 << J)) continue;
-        if (ckind == svp::CK_SLOT && !((k >> cslot) & 1)) continue;
-        constexpr int H = 1 << J;
-        C x = a[k], y = a[k + H], nx, ny;
-        if (kind == svp::K2_H) {
-            nx = x;
-            ny = y;
-            hbfly(nx, ny);
-        } else if (kind == svp::K2_HU) {
-            nx.x = x.x + y.x;
-            nx.y = x.y + y.y;
-            ny.x = x.x - y.x;
-            ny.y = x.y - y.y;
-        } else if (kind == svp::K2_X) {
-            nx = y;
-            ny = x;
-        } else {
-            nx = cmad2(u00, x, u01, y);
-            ny = cmad2(u10, x, u11, y);
-        }
-        a[k] = csel(tpred, nx, x);
-        a[k + H] = csel(tpred, ny, y);
-    }
-}
-
-// Block-resident pass. Work-group = one block of 2^l amplitudes: local bit i
-// is memory bit args.bits[i]; the other memory bits come from blockIdx. Each
-// thread holds R = 2^LOGR amplitudes in registers; register slot j stands for
-// local bit rb[j]; the remaining local bits, in ascending order, are the bits
-// of threadIdx. The program (args.nops ops) starts and ends in the canonical
-// layout: slot 0 = local bit 0, slots 1.. = the top LOGR-1 local bits, so
-// lanes walk consecutive memory and, for complex64, slots 0 and 1 form one
-// 16-byte access.
-// Largest work-group of a block-pass variant: big register tiles need the
-// VGPR budget of fewer waves per SIMD.
-// Unnormalized Hadamard on register slot J: (a, b) -> (a + b, a - b).
-template <int J, int R, typename C> __device__ __forceinline__ void k2_hu(C *a)
-{
-    constexpr int H = 1 << J;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        if (k & H) continue;
-        const C x = a[k], y = a[k + H];
-        a[k].x = x.x + y.x;
-        a[k].y = x.y + y.y;
-        a[k + H].x = x.x - y.x;
-        a[k + H].y = x.y - y.y;
-    }
-}
-
-template <typename T, int LOGR> constexpr int k2_max_threads()
-{
-    return (LOGR + (sizeof(T) == 8 ? 1 : 0)) >= 5 ? (LOGR + (sizeof(T) == 8 ? 1 : 0) >= 6 ? 256 : 512) : 1024;
-}
-
+// Interpreted block pass: the op list of the pass runs on every block (see
+// k2_body and K2Interp in k2_device.h).
 template <typename T, int LOGR>
 __global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
-k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, K2Args args)
+k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, svp::K2Args args)
 {
-    using C = typename CT<T>::type;
-    constexpr int R = 1 << LOGR;
     extern __shared__ unsigned char lds_raw[];
-    const int l = args.l;
-    const int tb = l - LOGR;
-    const uint32_t tid = threadIdx.x;
-
-    uint64_t base = 0;
-    {
-        const uint64_t bid = blockIdx.x;
-        for (int i = 0; i < args.n - l; ++i) base |= ((bid >> i) & 1ull) << args.nbits[i];
-    }
-    // Block-uniform phase factors of the diagonal runs: each is
-    // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in 64-bit
-    // fixed-point turns and evaluated once per work-group.
-    double2 *ufac = reinterpret_cast<double2 *>(lds_raw + (sizeof(C) << l));
-    if (args.nug > 0) {
-        const svp::UGroup *ug = reinterpret_cast<const svp::UGroup *>(args.table + args.ug_off);
-        for (int g = threadIdx.x; g < args.nug; g += blockDim.x) {
-            const svp::UTerm *tm = reinterpret_cast<const svp::UTerm *>(args.table + ug[g].term_off);
-            uint64_t acc = 0;
-            for (int j = 0; j < ug[g].nterms; ++j)
-                if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
-            double sn, cs;
-            sincospi(ldexp((double)(int64_t)acc, -63), &sn, &cs);
-            ufac[g] = make_double2(cs, sn);
-        }
-        __syncthreads();
-    }
-
-    int rb[LOGR];
-    rb[0] = 0;
-#pragma unroll
-    for (int j = 1; j < LOGR; ++j) rb[j] = tb + j;
-    uint32_t tloc = tid << 1;
-
-    // memory index of the thread's slot-0 amplitude in the canonical layout
-    uint64_t tmem0 = base;
-    for (int i = 0; i < tb; ++i) tmem0 |= (uint64_t)((tid >> i) & 1u) << args.bits[i + 1];
-    uint64_t roff[LOGR];
-#pragma unroll
-    for (int j = 0; j < LOGR; ++j) roff[j] = 1ull << args.bits[rb[j]];
-
-    C a[R];
-    if (sizeof(C) == 8 && args.vec2) {
-        // memory bit 0 is local bit 0 = slot 0: slots k, k+1 are adjacent
-#pragma unroll
-        for (int k = 0; k < R; k += 2) {
-            uint64_t addr = tmem0;
-#pragma unroll
-            for (int j = 1; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
-            const float4 v = *reinterpret_cast<const float4 *>(S + addr);
-            a[k] = mk<C>(v.x, v.y);
-            a[k + 1] = mk<C>(v.z, v.w);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            uint64_t addr = tmem0;
-#pragma unroll
-            for (int j = 0; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
-            a[k] = S[addr];
-        }
-    }
-
-    for (int oi = 0; oi < args.nops; ++oi) {
-        const svp::K2Op &op = ops[oi];
-        const int kind = op.kind;
-        if (kind == svp::K2_HU) {
-            // uncontrolled Hadamard without the 1/sqrt2 (applied once per pass)
-            switch (op.a) {
-            case 0: k2_hu<0, R>(a); break;
-            case 1: if constexpr (LOGR > 1) k2_hu<1, R>(a); break;
-            case 2: if constexpr (LOGR > 2) k2_hu<2, R>(a); break;
-            case 3: if constexpr (LOGR > 3) k2_hu<3, R>(a); break;
-            case 4: if constexpr (LOGR > 4) k2_hu<4, R>(a); break;
-            default: break;
-            }
-        } else if (kind == svp::K2_DIAGRUN) {
-            // one phase multiply per amplitude for a run of diagonal gates:
-            // slot k in kmask gets Q[k] (k in qmask) times the thread factor
-            // U[uidx] * wave_table[wave] * lane_table[lane], all in FP64 and
-            // rounded once
-            const svp::DiagRec *rec = reinterpret_cast<const svp::DiagRec *>(args.table + op.a);
-            const double2 *qt = reinterpret_cast<const double2 *>(rec + 1);
-            const uint32_t kmask = rec->kmask, qmask = rec->qmask;
-            double2 f = make_double2(1.0, 0.0);
-            if (rec->has_group) {
-                const svp::DiagGroup &G = rec->g;
-                bool on = true;
-                if (G.cond_kind == 1) on = (base >> G.cond_bit) & 1ull;
-                else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1u;
-                if (on) {
-                    if (G.uidx >= 0) f = ufac[G.uidx];
-                    if (G.wave_off >= 0)
-                        f = cmul(f, reinterpret_cast<const double2 *>(args.table + G.wave_off)[tid >> 6]);
-                    if (G.lane_off >= 0)
-                        f = cmul(f, reinterpret_cast<const double2 *>(args.table + G.lane_off)[tid & 63u]);
-                }
-            }
-            const C fc = mk<C>(f.x, f.y);
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                if (!((kmask >> k) & 1u)) continue;
-                C Fk = fc;
-                if ((qmask >> k) & 1u) {
-                    const double2 F = cmul(qt[k], f);
-                    Fk = mk<C>(F.x, F.y);
-                }
-                a[k] = cmul(Fk, a[k]);
-            }
-        } else if (kind == svp::K2_LAYOUT) {
-            {
-                const uint32_t tsw = swz<C>(tloc) * (uint32_t)sizeof(C);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    uint32_t kp = 0;
-#pragma unroll
-                    for (int j = 0; j < LOGR; ++j)
-                        if ((k >> j) & 1) kp |= 1u << rb[j];
-                    *reinterpret_cast<C *>(lds_raw + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C)))) = a[k];
-                }
-            }
-            __syncthreads();
-            uint32_t x = tid;
-#pragma unroll
-            for (int j = 0; j < LOGR; ++j) {
-                rb[j] = (op.a >> (5 * j)) & 31;
-                x = insert0_32(x, rb[j]);  // rb ascending: zeros land on register bits
-            }
-            tloc = x;
-            {
-                const uint32_t tsw = swz<C>(tloc) * (uint32_t)sizeof(C);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    uint32_t kp = 0;
-#pragma unroll
-                    for (int j = 0; j < LOGR; ++j)
-                        if ((k >> j) & 1) kp |= 1u << rb[j];
-                    a[k] = *reinterpret_cast<const C *>(lds_raw + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C))));
-                }
-            }
-            __syncthreads();
-        } else if (kind == svp::K2_SCALE) {
-            const T sc = (T)op.v[0];
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                a[k].x *= sc;
-                a[k].y *= sc;
-            }
-        } else if (kind == svp::K2_PHASE) {
-            const bool tpred = ((tloc & (uint32_t)op.m0) == (uint32_t)op.m0) && ((base & op.m1) == op.m1);
-            const C z = mk<C>(op.v[0], op.v[1]);
-            const int rmask = op.a;
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                if ((k & rmask) != rmask) continue;
-                a[k] = csel(tpred, cmul(z, a[k]), a[k]);
-            }
-        } else if (kind == svp::K2_DIAG) {
-            const bool tpred = ((tloc & (uint32_t)op.m0) == (uint32_t)op.m0) && ((base & op.m1) == op.m1);
-            const C d0 = mk<C>(op.v[0], op.v[1]), d1 = mk<C>(op.v[2], op.v[3]);
-            const int slot = op.a, rmask = op.c;
-            if (slot >= 0) {
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    if ((k & rmask) != rmask) continue;
-                    const C d = csel(((k >> slot) & 1) != 0, d1, d0);
-                    a[k] = csel(tpred, cmul(d, a[k]), a[k]);
-                }
-            } else {
-                const bool sel = code_bit(tloc, base, op.b);
-                const C d = csel(sel, d1, d0);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    if ((k & rmask) != rmask) continue;
-                    a[k] = csel(tpred, cmul(d, a[k]), a[k]);
-                }
-            }
-        } else {
-            const int ckind = op.b;
-            const bool tpred = (ckind == svp::CK_MEM) ? code_bit(tloc, base, op.c) : true;
-            const int cslot = op.c;
-            switch (op.a) {
-            case 0: k2_pairs<0, R>(a, kind, op.v, tpred, ckind, cslot); break;
-            case 1: if constexpr (LOGR > 1) k2_pairs<1, R>(a, kind, op.v, tpred, ckind, cslot); break;
-            case 2: if constexpr (LOGR > 2) k2_pairs<2, R>(a, kind, op.v, tpred, ckind, cslot); break;
-            case 3: if constexpr (LOGR > 3) k2_pairs<3, R>(a, kind, op.v, tpred, ckind, cslot); break;
-            case 4: if constexpr (LOGR > 4) k2_pairs<4, R>(a, kind, op.v, tpred, ckind, cslot); break;
-            default: break;
-            }
-        }
-    }
-
-    // the program ends in the canonical layout
-    if (sizeof(C) == 8 && args.vec2) {
-#pragma unroll
-        for (int k = 0; k < R; k += 2) {
-            uint64_t addr = tmem0;
-#pragma unroll
-            for (int j = 1; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
-            float4 v;
-            v.x = (float)a[k].x;
-            v.y = (float)a[k].y;
-            v.z = (float)a[k + 1].x;
-            v.w = (float)a[k + 1].y;
-            *reinterpret_cast<float4 *>(S + addr) = v;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            uint64_t addr = tmem0;
-#pragma unroll
-            for (int j = 0; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
-            S[addr] = a[k];
-        }
-    }
+    k2_body<T, LOGR>(S, args, lds_raw, K2Interp{ops, args.nops, args.l});
 }
 
 template <typename T, int LOGR>
@@ -578,9 +211,23 @@ static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hi
     }
     const unsigned threads = 1u << (a.l - LOGR);
     const uint64_t blocks = 1ull << (a.n - a.l);
-    if (threads > (unsigned)k2_max_threads<T, LOGR>() || blocks > 0x7fffffffull)
-        return hipErrorInvalidConfiguration;
-    k2_kernel<T, LOGR><<<(unsigned)blocks, threads, lds, st>>>((C *)S, ops, a);
+    if (threads > (unsigned)k2_max_threads<T, LOGR>()) return hipErrorInvalidConfiguration;
+    // persistent grid: as many work-groups as fit on the device at once
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k2_kernel<T, LOGR>,
+                                                                (int)threads, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    uint64_t grid = (uint64_t)per_cu * (uint64_t)cus;
+    if (grid > blocks) grid = blocks;
+    k2_kernel<T, LOGR><<<(unsigned)grid, threads, lds, st>>>((C *)S, ops, a);
     return hipGetLastError();
 }
 

@@ -11,18 +11,7 @@
 
 namespace svk {
 
-// Block-pass arguments passed by value.
-struct K2Args {
-    int n;
-    int l;
-    int nops;
-    int nug;                 // block-uniform factor groups
-    const uint8_t *table;    // device copy of Plan::table
-    int ug_off;              // byte offset of the UGroup array
-    int vec2;                // 1: memory bit 0 is local bit 0 (16-byte complex64 pairs)
-    int8_t bits[48];         // memory bit of each local bit, ascending
-    int8_t nbits[48];        // memory bits outside the block, ascending
-};
+using K2Args = svp::K2Args;
 
 hipError_t init_zero_state(void *S, int n, int dtype, hipStream_t st);
 hipError_t k1_gate(void *S, int n, int dtype, const svp::MGate &g, hipStream_t st);

@@ -25,6 +25,8 @@
 #include <string>
 #include <vector>
 
+#include "k2_abi.h"
+
 namespace svp {
 
 // Gate classes after matrix construction.
@@ -43,66 +45,9 @@ struct MGate {
     double th0, th1;
 };
 
-// Block-pass ops (device program). Field meaning per kind is documented at
-// the kernel that executes them.
-enum K2Kind {
-    K2_LAYOUT = 0,   // a: packed register local bits (5 bits each)
-    K2_DENSE = 1,    // a: slot; b: control kind; c: control slot or memory bit
-    K2_H = 2,        // as K2_DENSE, Hadamard
-    K2_X = 3,        // as K2_DENSE, exchange
-    K2_PHASE = 4,    // m0: memory-bit mask; a: slot mask; v[0..1]: factor
-    K2_DIAG = 5,     // a: target slot or -1; b: target memory bit; c: slot mask;
-                     // m0: memory-bit mask; v[0..1]: d0, v[2..3]: d1
-    K2_DIAGRUN = 6,  // a: byte offset of a DiagRec in the table buffer
-    K2_HU = 7,       // unnormalized Hadamard (a+b, a-b) on slot a, no control
-    K2_SCALE = 8,    // every amplitude times v[0]
-};
-enum CtlKind { CK_NONE = 0, CK_SLOT = 1, CK_MEM = 2 };
-
-struct K2Op {
-    int32_t kind, a, b, c;
-    uint64_t m0, m1;
-    double v[8];
-};
 static_assert(sizeof(K2Op) == 96, "K2Op layout");
-
-// One thread-dependent factor of a diagonal run: applied to the amplitudes
-// whose register slots cover rmask, when the block-uniform or wave-uniform
-// condition holds. factor = U[uidx] * wave_table[wave] * lane_table[lane].
-struct DiagGroup {
-    int32_t rmask;
-    int32_t cond_kind;  // 0 none, 1 memory bit of the block base, 2 thread-id bit (>= 6)
-    int32_t cond_bit;
-    int32_t uidx;       // block-uniform factor index, -1 none
-    int32_t lane_off;   // byte offset of 64 complex doubles, -1 none
-    int32_t wave_off;   // byte offset of 2^(waves) complex doubles, -1 none
-    int32_t pad0, pad1;
-};
 static_assert(sizeof(DiagGroup) == 32, "DiagGroup layout");
-
-// One op of a diagonal run; followed in the table by 2^r complex doubles Q[k]:
-// the constant factor of register pattern k. Amplitude slot k in kmask is
-// multiplied by (k in qmask ? Q[k] : 1) * (has_group ? group factor : 1).
-// The planner guarantees that a group covers every slot in kmask.
-struct DiagRec {
-    uint32_t kmask;
-    uint32_t qmask;
-    int32_t has_group;
-    int32_t pad;
-    DiagGroup g;
-};
 static_assert(sizeof(DiagRec) == 48, "DiagRec layout");
-
-// Block-uniform factor: e^{2 pi i sum angle_j [base covers tmask_j]} with
-// angles as 64-bit fixed-point turns; computed once per work-group.
-struct UGroup {
-    int32_t term_off;   // byte offset of the UTerm array
-    int32_t nterms;
-};
-struct UTerm {
-    uint64_t tmask;
-    uint64_t angle;
-};
 
 enum StepKind {
     ST_K1 = 0,  // one plain sweep for one gate

@@ -8,11 +8,13 @@
 // or table emitted by the planner is caught without a GPU. It is not linked
 // into the simulator library.
 #include <cmath>
+#include <cstdio>
 #include <complex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
 
+#include "../../paper_2605_15098_amd/csrc/jit.h"
 #include "../../paper_2605_15098_amd/csrc/plan.h"
 
 using cd = std::complex<double>;
@@ -260,4 +262,38 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
     counts_out[2] = (int64_t)plan.ops.size();
     counts_out[3] = (int64_t)plan.table.size();
     return 0;
+}
+
+// Plan the circuit and compile every generated block-pass kernel (no GPU
+// needed). Returns the number of kernels compiled, or -1 with the first
+// compiler log copied to log_out.
+extern "C" int emu_jit_check(int n, int dtype, int l, int logr, int policy, int remap, int diag_free, int fuse_k,
+                             const void *gates, size_t m, char *log_out, size_t log_cap)
+{
+    PlanConfig c;
+    c.n = n;
+    c.dtype = dtype;
+    c.mode = 1;
+    c.l = l;
+    c.logr = logr;
+    c.policy = policy;
+    c.remap = remap;
+    c.diag_free = diag_free;
+    c.fuse_k = fuse_k;
+    std::vector<int> l2p(n);
+    for (int q = 0; q < n; ++q) l2p[q] = q;
+    Plan plan;
+    if (!make_plan(c, reinterpret_cast<const RawGate *>(gates), m, l2p, plan).empty()) return -2;
+    int count = 0;
+    for (const Step &st : plan.steps) {
+        if (st.kind != ST_K2) continue;
+        const std::string src = svj::generate(st, plan, dtype);
+        const std::string log = svj::compile_check(src);
+        if (!log.empty()) {
+            std::snprintf(log_out, log_cap, "%s\n---- source ----\n%s", log.c_str(), src.c_str());
+            return -1;
+        }
+        ++count;
+    }
+    return count;
 }

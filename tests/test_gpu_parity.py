@@ -221,3 +221,24 @@ def test_injected_launch_failure_leaves_handle_destroyable():
         s.apply(W.qpe_gates(6, 0.3))
     assert e.value.status == sv.SV_ERR_DEVICE
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_compiled_passes_match_interpreter_bitwise(dtype, monkeypatch):
+    """Block passes compiled for their op lists run the same handlers in the
+    same order as the op interpreter: identical bits."""
+    rng = np.random.default_rng(31)
+    for n, l, depth in ((9, 6, 80), (14, 10, 150), (16, 12, 200)):
+        g = np.concatenate([W.random_mixed_circuit(n, depth, rng), W.random_circuit(n, depth, rng)])
+        init = rand_state(n, rng)
+        outs = []
+        for jit in ("0", "1"):
+            monkeypatch.setenv("SV_JIT", jit)
+            for sched in (sv.schedule(block_qubits=l), sv.paper_schedule(l)):
+                log(f"case jit={jit} n={n} dtype={dtype}")
+                got, _, _ = run(n, dtype, g, sched, init)
+                outs.append(got)
+        want = oracle.apply(n, g, init)
+        for i in range(2):
+            assert np.array_equal(outs[i].view(np.uint8), outs[i + 2].view(np.uint8))
+            assert np.max(np.abs(outs[i] - want)) <= TOL[dtype]

@@ -19,8 +19,10 @@ from paper_2605_15098_amd import workloads as W
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "emu", "k2_emulator.cpp"),
-       os.path.join(ROOT, "paper_2605_15098_amd", "csrc", "plan.cpp")]
+CSRC = os.path.join(ROOT, "paper_2605_15098_amd", "csrc")
+SRC = [os.path.join(HERE, "emu", "k2_emulator.cpp"), os.path.join(CSRC, "plan.cpp"),
+       os.path.join(CSRC, "jit.cpp")]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 LIB = os.path.join(HERE, "emu", "libk2emu.so")
 _lib = None
 
@@ -28,16 +30,24 @@ _lib = None
 def emu():
     global _lib
     if _lib is None:
-        newest = max(os.path.getmtime(p) for p in SRC + [SRC[1].replace(".cpp", ".h")])
+        from paper_2605_15098_amd import build as B
+        B.write_jit_sources()
+        deps = SRC + [os.path.join(CSRC, f) for f in ("plan.h", "k2_abi.h", "k2_device.h", "jit.h")]
+        newest = max(os.path.getmtime(p) for p in deps)
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
             tmp = LIB + f".tmp{os.getpid()}"
-            subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp] + SRC, check=True)
+            subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-D__HIP_PLATFORM_AMD__",
+                            f"-I{ROCM}/include", "-o", tmp] + SRC +
+                           [f"-L{ROCM}/lib", "-lhiprtc", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"], check=True)
             os.replace(tmp, LIB)
         lib = ctypes.CDLL(LIB)
         lib.emu_apply.argtypes = [ctypes.c_int] * 10 + [ctypes.c_void_p, ctypes.c_size_t,
                                                         ctypes.POINTER(ctypes.c_double),
                                                         ctypes.POINTER(ctypes.c_int64)]
         lib.emu_apply.restype = ctypes.c_int
+        lib.emu_jit_check.argtypes = [ctypes.c_int] * 8 + [ctypes.c_void_p, ctypes.c_size_t,
+                                                           ctypes.c_char_p, ctypes.c_size_t]
+        lib.emu_jit_check.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -121,3 +131,26 @@ def test_non_unit_diagonal_u2():
     want = oracle.apply(n, g)
     got, _ = run(n, g, l=6)
     assert np.max(np.abs(got - want)) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("case", ["qpe", "random", "diag", "strict"])
+def test_generated_pass_kernels_compile(case, dtype):
+    """Every block-pass kernel the run-time compiler writes must compile for
+    gfx950 (hipRTC runs without a GPU)."""
+    rng = np.random.default_rng(17)
+    n, l, logr, fuse = 16, (13 if dtype == 0 else 12), 4, 1
+    if case == "qpe":
+        g = W.qpe_gates(n, 0.3)
+    elif case == "random":
+        g = W.random_mixed_circuit(n, 120, rng)
+    elif case == "diag":
+        g = W.random_circuit(n, 150, rng)
+        logr = 5 if dtype == 0 else 3
+    else:
+        g = W.random_mixed_circuit(n, 60, rng)
+        fuse = 0
+    buf = ctypes.create_string_buffer(1 << 16)
+    gg = np.ascontiguousarray(g)
+    cnt = emu().emu_jit_check(n, dtype, l, logr, 1, 0, 1, fuse, gg.ctypes.data, len(gg), buf, len(buf))
+    assert cnt > 0, buf.value.decode(errors="replace")[:4000]
