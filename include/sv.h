@@ -168,6 +168,14 @@ sv_status sv_set_stream(sv_handle h, void *hip_stream);
  * (fuse_k > 6), DEVICE. No gate is applied when validation fails. */
 sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *s);
 
+/* Compile ahead of time the block-pass kernels that `repeats` consecutive
+ * sv_apply_circuit calls of this circuit and schedule will use from the
+ * current layout (a circuit whose SWAP gates relabel qubits changes the
+ * layout the next call starts from). Block passes are compiled for their op
+ * lists at run time and cached; without this call the first use of a pass
+ * compiles it. No state is changed and nothing runs on the device. */
+sv_status sv_prepare(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *s, int repeats);
+
 /* Many independent circuits (one per handle, all of one dtype) in one
  * persistent kernel launch, replayed from a captured HIP graph when the same
  * batch shape is applied again. Each handle's state is updated as by

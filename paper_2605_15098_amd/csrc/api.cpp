@@ -222,6 +222,7 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
 
 sv_status run_plan(sv_handle h, const svp::Plan &plan)
 {
+    const auto tu0 = std::chrono::steady_clock::now();
     if (!plan.ops.empty()) {
         const size_t need = plan.ops.size();
         if (need > h->dops_cap) {
@@ -264,15 +265,18 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
     // first event so device time covers only the kernels.
     const char *jenv = std::getenv("SV_JIT");
     const bool use_jit = !(jenv && jenv[0] == '0');
+    const bool trace = std::getenv("SV_TRACE_HOST") != nullptr;
+    const auto tp0 = std::chrono::steady_clock::now();
+    if (trace)
+        std::fprintf(stderr, "[sv] upload %.3f ms\n", std::chrono::duration<double, std::milli>(tp0 - tu0).count());
     std::vector<const void *> jit(plan.steps.size(), nullptr);
     if (use_jit) {
-        for (size_t i = 0; i < plan.steps.size(); ++i) {
-            if (plan.steps[i].kind != svp::ST_K2) continue;
-            std::string err;
-            hipError_t e = svj::prepare(plan.steps[i], plan, h->dtype, &jit[i], &err);
-            if (e != hipSuccess) return fail(SV_ERR_DEVICE, err.empty() ? std::string("pass compilation: ") + hipGetErrorString(e) : err);
-        }
+        std::string err;
+        hipError_t e = svj::prepare_plan(plan, h->dtype, jit, &err);
+        if (e != hipSuccess)
+            return fail(SV_ERR_DEVICE, err.empty() ? std::string("pass compilation: ") + hipGetErrorString(e) : err);
     }
+    const auto tp1 = std::chrono::steady_clock::now();
     h->kev_kind.clear();
     if (h->kernel_timing) {
         const size_t need = 2 * plan.steps.size();
@@ -322,6 +326,12 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
     }
     SV_HIP(hipEventRecord(h->ev1, h->stream), "hipEventRecord");
     h->timed = true;
+    if (trace) {
+        const auto tp2 = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[sv] prepare %.3f ms, launch %.3f ms, %zu steps\n",
+                     std::chrono::duration<double, std::milli>(tp1 - tp0).count(),
+                     std::chrono::duration<double, std::milli>(tp2 - tp1).count(), plan.steps.size());
+    }
     return SV_OK;
 }
 
@@ -486,6 +496,28 @@ sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv
     std::memset(&h->st, 0, sizeof(h->st));
     fill_stats(&h->st, c, plan);
     h->st.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return SV_OK;
+}
+
+sv_status sv_prepare(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *s, int repeats)
+{
+    if (sv_status st = check_handle(h)) return st;
+    if (sv_status st = check_schedule(s, h->dtype)) return st;
+    if (repeats < 1 || repeats > 64) return fail(SV_ERR_INVALID_ARG, "repeats must be in [1, 64]");
+    const char *jenv = std::getenv("SV_JIT");
+    if (jenv && jenv[0] == '0') return SV_OK;
+    svp::PlanConfig c = config_from(h, s);
+    std::vector<int> l2p = h->l2p;
+    for (int r = 0; r < repeats; ++r) {
+        svp::Plan plan;
+        std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, l2p, plan);
+        if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+        std::vector<const void *> handles;
+        hipError_t e = svj::prepare_plan(plan, h->dtype, handles, &err);
+        if (e != hipSuccess)
+            return fail(SV_ERR_DEVICE, err.empty() ? std::string("pass compilation: ") + hipGetErrorString(e) : err);
+        l2p = plan.l2p_after;
+    }
     return SV_OK;
 }
 

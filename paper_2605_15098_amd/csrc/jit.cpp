@@ -24,11 +24,14 @@ namespace {
 
 #include "jit_src.inc"  // kJitAbiH, kJitDeviceH: text of k2_abi.h and k2_device.h
 
-struct Entry {
-    hipModule_t mod = nullptr;
+struct Kernel {
     hipFunction_t fn = nullptr;
     int per_cu = 0;
     unsigned threads = 0;
+};
+struct Entry {
+    hipModule_t mod = nullptr;
+    std::vector<Kernel> kernels;
 };
 
 std::mutex g_mu;
@@ -48,13 +51,12 @@ std::string u64s(uint64_t x) { return std::to_string(x) + "ull"; }
 
 namespace svj {
 
-std::string generate(const svp::Step &s, const svp::Plan &plan, int dtype)
+static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int dtype, int idx)
 {
     const int r = s.logr, l = s.l;
     const int R = 1 << r;
     std::ostringstream o;
-    o << "#include \"k2_device.h\"\nusing namespace svk;\n";
-    o << "struct Prog {\n  template <typename T, int LOGR>\n"
+    o << "struct Prog" << idx << " {\n  template <typename T, int LOGR>\n"
          "  __device__ __forceinline__ void run(typename CT<T>::type *a, K2Ctx &cx) const {\n"
          "    using C = typename CT<T>::type;\n    constexpr int R = 1 << LOGR;\n    (void)R;\n";
     std::vector<int> rb(r);
@@ -126,14 +128,30 @@ std::string generate(const svp::Step &s, const svp::Plan &plan, int dtype)
     const unsigned threads = 1u << (l - r);
     const size_t amp = dtype == 0 ? 8 : 16;
     const size_t lds = ((amp << l) + (size_t)s.nug * 16 + 15) / 16 * 16;
-    o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") svk2_pass(CT<" << T
+    o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") svk2_pass_" << idx << "(CT<" << T
       << ">::type *__restrict__ S, svp::K2Args args) {\n"
       << "  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[" << (lds > 0 ? lds : 16) << "];\n"
-      << "  k2_body<" << T << ", " << r << ">(S, args, lds_raw, Prog{});\n}\n";
+      << "  k2_body<" << T << ", " << r << ">(S, args, lds_raw, Prog" << idx << "{});\n}\n";
     return o.str();
 }
 
-static hipError_t compile(const std::string &src, Entry &e, std::string *err)
+std::string generate(const svp::Step &s, const svp::Plan &plan, int dtype)
+{
+    return "#include \"k2_device.h\"\nusing namespace svk;\n" + generate_pass(s, plan, dtype, 0);
+}
+
+// All block passes of a plan in one translation unit (one compile); kernel
+// i is svk2_pass_<i> for the i-th block pass.
+std::string generate_plan(const svp::Plan &plan, int dtype)
+{
+    std::string src = "#include \"k2_device.h\"\nusing namespace svk;\n";
+    int idx = 0;
+    for (const svp::Step &s : plan.steps)
+        if (s.kind == svp::ST_K2) src += generate_pass(s, plan, dtype, idx++);
+    return src;
+}
+
+static hipError_t compile(const std::string &src, std::vector<char> &code, std::string *err)
 {
     hiprtcProgram prog;
     const char *headers[] = {kJitAbiH, kJitDeviceH};
@@ -142,9 +160,9 @@ static hipError_t compile(const std::string &src, Entry &e, std::string *err)
         if (err) *err = "hiprtcCreateProgram failed";
         return hipErrorInvalidValue;
     }
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-                          "-packed-fp32-ops"};
-    const hiprtcResult rc = hiprtcCompileProgram(prog, 7, opts);
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                          "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, 8, opts);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
@@ -156,13 +174,10 @@ static hipError_t compile(const std::string &src, Entry &e, std::string *err)
     }
     size_t cs = 0;
     hiprtcGetCodeSize(prog, &cs);
-    std::vector<char> code(cs);
+    code.resize(cs);
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
-    hipError_t he = hipModuleLoadData(&e.mod, code.data());
-    if (he != hipSuccess) return he;
-    he = hipModuleGetFunction(&e.fn, e.mod, "svk2_pass");
-    return he;
+    return hipSuccess;
 }
 
 std::string compile_check(const std::string &src)
@@ -172,10 +187,10 @@ std::string compile_check(const std::string &src)
     const char *names[] = {"k2_abi.h", "k2_device.h"};
     if (hiprtcCreateProgram(&prog, src.c_str(), "svk2_pass.hip", 2, headers, names) != HIPRTC_SUCCESS)
         return "hiprtcCreateProgram failed";
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-                          "-packed-fp32-ops"};
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                          "-target-feature", "-Xclang", "-packed-fp32-ops"};
     std::string out;
-    if (hiprtcCompileProgram(prog, 7, opts) != HIPRTC_SUCCESS) {
+    if (hiprtcCompileProgram(prog, 8, opts) != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
         out.assign(ls, '\0');
@@ -186,9 +201,13 @@ std::string compile_check(const std::string &src)
     return out;
 }
 
-hipError_t prepare(const svp::Step &s, const svp::Plan &plan, int dtype, const void **handle, std::string *err)
+hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void *> &handles, std::string *err)
 {
-    const std::string src = generate(s, plan, dtype);
+    handles.assign(plan.steps.size(), nullptr);
+    bool any = false;
+    for (const svp::Step &s : plan.steps) any = any || s.kind == svp::ST_K2;
+    if (!any) return hipSuccess;
+    const std::string src = generate_plan(plan, dtype);
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_cus == 0) {
         int dev = 0;
@@ -198,22 +217,36 @@ hipError_t prepare(const svp::Step &s, const svp::Plan &plan, int dtype, const v
     }
     auto it = g_cache.find(src);
     if (it == g_cache.end()) {
+        std::vector<char> code;
+        hipError_t he = compile(src, code, err);
+        if (he != hipSuccess) return he;
         Entry e;
-        hipError_t he = compile(src, e, err);
+        he = hipModuleLoadData(&e.mod, code.data());
         if (he != hipSuccess) return he;
-        e.threads = 1u << (s.l - s.logr);
-        he = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&e.per_cu, e.fn, (int)e.threads, 0);
-        if (he != hipSuccess) return he;
-        if (e.per_cu < 1) return hipErrorInvalidConfiguration;
-        it = g_cache.emplace(src, e).first;
+        int idx = 0;
+        for (const svp::Step &s : plan.steps) {
+            if (s.kind != svp::ST_K2) continue;
+            Kernel k;
+            const std::string name = "svk2_pass_" + std::to_string(idx++);
+            he = hipModuleGetFunction(&k.fn, e.mod, name.c_str());
+            if (he != hipSuccess) return he;
+            k.threads = 1u << (s.l - s.logr);
+            he = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&k.per_cu, k.fn, (int)k.threads, 0);
+            if (he != hipSuccess) return he;
+            if (k.per_cu < 1) return hipErrorInvalidConfiguration;
+            e.kernels.push_back(k);
+        }
+        it = g_cache.emplace(src, std::move(e)).first;
     }
-    *handle = &it->second;
+    size_t k = 0;
+    for (size_t i = 0; i < plan.steps.size(); ++i)
+        if (plan.steps[i].kind == svp::ST_K2) handles[i] = &it->second.kernels[k++];
     return hipSuccess;
 }
 
 hipError_t launch(const void *handle, void *S, const svp::K2Args &a, hipStream_t st)
 {
-    const Entry &e = *static_cast<const Entry *>(handle);
+    const Kernel &e = *static_cast<const Kernel *>(handle);
     const uint64_t blocks = 1ull << (a.n - a.l);
     uint64_t grid = (uint64_t)e.per_cu * (uint64_t)g_cus;
     if (grid > blocks) grid = blocks;

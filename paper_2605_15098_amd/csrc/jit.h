@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "plan.h"
 
@@ -12,9 +13,14 @@ namespace svj {
 // Source text of the kernel for pass s of plan (complex64: dtype 0).
 std::string generate(const svp::Step &s, const svp::Plan &plan, int dtype);
 
-// Compile (or fetch from the cache) the kernel of pass s; *handle identifies
-// it for launch(). On a compile error, *err holds the compiler log.
-hipError_t prepare(const svp::Step &s, const svp::Plan &plan, int dtype, const void **handle, std::string *err);
+// Compile (or fetch from the cache) the kernels of every block pass of the
+// plan, as one module; handles[i] identifies step i's kernel for launch()
+// (nullptr for steps that are not block passes). On a compile error, *err
+// holds the compiler log.
+hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void *> &handles, std::string *err);
+
+// Source of all block passes of a plan (what prepare_plan compiles).
+std::string generate_plan(const svp::Plan &plan, int dtype);
 
 // Launch a prepared pass on `st` with a persistent grid.
 hipError_t launch(const void *handle, void *S, const svp::K2Args &a, hipStream_t st);

@@ -93,6 +93,7 @@ _SIGS = {
     "sv_reset": ([_VP], ctypes.c_int32),
     "sv_set_stream": ([_VP, _VP], ctypes.c_int32),
     "sv_apply_circuit": ([_VP, _VP, ctypes.c_size_t, ctypes.POINTER(sv_schedule)], ctypes.c_int32),
+    "sv_prepare": ([_VP, _VP, ctypes.c_size_t, ctypes.POINTER(sv_schedule), ctypes.c_int], ctypes.c_int32),
     "sv_apply_batch": ([ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP),
                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(sv_schedule)], ctypes.c_int32),
     "sv_probabilities": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _VP], ctypes.c_int32),
@@ -195,6 +196,12 @@ def sv_apply_circuit(h, gates, sched: Optional[sv_schedule] = None) -> None:
     g = _gates(gates)
     _check(load().sv_apply_circuit(_VP(h), g.ctypes.data if len(g) else None, len(g),
                                    _sched_ptr(sched)))
+
+
+def sv_prepare(h, gates, sched: Optional[sv_schedule] = None, repeats: int = 1) -> None:
+    g = _gates(gates)
+    _check(load().sv_prepare(_VP(h), g.ctypes.data if len(g) else None, len(g), _sched_ptr(sched),
+                             int(repeats)))
 
 
 def sv_apply_batch(handles: Sequence[int], gate_lists: Sequence[np.ndarray],

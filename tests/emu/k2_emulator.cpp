@@ -285,15 +285,12 @@ extern "C" int emu_jit_check(int n, int dtype, int l, int logr, int policy, int 
     Plan plan;
     if (!make_plan(c, reinterpret_cast<const RawGate *>(gates), m, l2p, plan).empty()) return -2;
     int count = 0;
-    for (const Step &st : plan.steps) {
-        if (st.kind != ST_K2) continue;
-        const std::string src = svj::generate(st, plan, dtype);
-        const std::string log = svj::compile_check(src);
-        if (!log.empty()) {
-            std::snprintf(log_out, log_cap, "%s\n---- source ----\n%s", log.c_str(), src.c_str());
-            return -1;
-        }
-        ++count;
+    for (const Step &st : plan.steps) count += st.kind == ST_K2;
+    const std::string src = svj::generate_plan(plan, dtype);
+    const std::string log = svj::compile_check(src);
+    if (!log.empty()) {
+        std::snprintf(log_out, log_cap, "%s\n---- source ----\n%s", log.c_str(), src.c_str());
+        return -1;
     }
     return count;
 }

@@ -59,7 +59,11 @@ def rand_state(n, rng):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 9, 13, 15])
-def test_random_circuits_all_schedules(n, dtype):
+def test_random_circuits_all_schedules(n, dtype, monkeypatch):
+    # the broad sweep runs block passes through the op interpreter (one
+    # compile per program would dominate); compiled passes are checked bit
+    # for bit against it below
+    monkeypatch.setenv("SV_JIT", "0")
     rng = np.random.default_rng(1000 + n)
     g = W.random_mixed_circuit(n, 60, rng)
     init = rand_state(n, rng)
