@@ -176,13 +176,27 @@ sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv
  * compiles it. No state is changed and nothing runs on the device. */
 sv_status sv_prepare(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *s, int repeats);
 
-/* Many independent circuits (one per handle, all of one dtype) in one
- * persistent kernel launch, replayed from a captured HIP graph when the same
- * batch shape is applied again. Each handle's state is updated as by
- * sv_apply_circuit with a partitioned schedule. Handles must be distinct and
- * on the same device. */
+/* Many independent circuits, one per handle (all of one dtype, distinct
+ * handles, one device), in one persistent kernel launch captured in a HIP
+ * graph. Each instance is planned with the partitioned schedule at one shared
+ * block size (the schedule's, capped by the smallest instance); work-groups
+ * are split among instances in proportion to their work and run each
+ * instance's passes in order, meeting at a device-scope counter barrier
+ * between passes. The graph is cached by a hash of the gate lists, layouts,
+ * buffers and schedule, so the same batch applied again replays it. Runs on
+ * the first handle's stream and synchronizes it (the barrier's error flag is
+ * checked: SV_ERR_DEVICE if a barrier wait timed out). Schedules that are not
+ * partitioned with virtual remap, or more instances than resident
+ * work-groups, are applied one circuit after another. Each handle's stats
+ * receive its own counts and the batch's device time. */
 sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m,
                          const sv_schedule *s);
+
+/* Exhaustive batch tuner: times sv_apply_batch on scratch copies of the
+ * states for every block size from the smallest instance size down three
+ * qubits (at least 7) and diagonal-run combining off/on, and returns the
+ * fastest schedule (median of three runs). The states are not changed. */
+sv_status sv_tune_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m, sv_schedule *out);
 
 /* Probabilities |alpha|^2 in FP64 (measurement, the meters of the QPE
  * figure). nq = 0: all 2^n in logical order. Otherwise the marginal over the

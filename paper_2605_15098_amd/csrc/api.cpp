@@ -521,15 +521,6 @@ sv_status sv_prepare(sv_handle h, const sv_gate *gates, size_t m, const sv_sched
     return SV_OK;
 }
 
-sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m,
-                         const sv_schedule *s)
-{
-    if (count < 0 || (count > 0 && (!hs || !gates || !m))) return fail(SV_ERR_INVALID_ARG, "bad batch arrays");
-    for (int i = 0; i < count; ++i)
-        if (sv_status st = sv_apply_circuit(hs[i], gates[i], m[i], s)) return st;
-    return SV_OK;
-}
-
 sv_status sv_stats_get(sv_handle h, sv_stats *out)
 {
     if (sv_status s = check_handle(h)) return s;
@@ -753,6 +744,410 @@ sv_status sv_tune(sv_handle h, const sv_gate *gates, size_t m, int mode, sv_sche
     (void)mode;
     (void)out;
     return fail(SV_ERR_UNSUPPORTED, "tuner not available in this build");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+// One prepared batch: its device arrays and captured graph, keyed by a hash
+// of everything its plans depend on.
+struct BatchEntry {
+    uint64_t key = 0;
+    int dtype = 0, logr = 4, count = 0;
+    unsigned grid = 0, threads = 0;
+    size_t lds = 0;
+    void *dbuf = nullptr;
+    unsigned *ctrs = nullptr;  // count barrier counters, then the error flag
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::vector<int>> l2p_after;
+    std::vector<svp::PlanStats> stats;
+    int l = 0;
+    ~BatchEntry()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (dbuf) hipFree(dbuf);
+    }
+};
+
+std::mutex g_batch_mu;
+std::vector<BatchEntry *> g_batches;  // most recent last
+int *g_err_host = nullptr;
+
+uint64_t mix64(uint64_t h, uint64_t x)
+{
+    h ^= x + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    h *= 0xff51afd7ed558ccdull;
+    return h ^ (h >> 33);
+}
+
+uint64_t hash_bytes(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, b + i, 8);
+        h = mix64(h, w);
+    }
+    uint64_t tail = 0;
+    std::memcpy(&tail, b + i, n - i);
+    return mix64(h, tail ^ n);
+}
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// Build (or fetch) the batch for these handles; nullptr + message on failure.
+// *sequential is set when the schedule does not run as one launch.
+BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m, const sv_schedule *s,
+                      bool *sequential, std::string *err)
+{
+    *sequential = false;
+    const int dtype = hs[0]->dtype;
+    svp::PlanConfig base = config_from(hs[0], s);
+    int min_n = 64;
+    for (int i = 0; i < count; ++i) min_n = std::min(min_n, hs[i]->n);
+    int l = base.l > 0 ? base.l : svp::default_block_qubits(dtype);
+    l = std::min(l, min_n);
+    const int logr = std::min(4, l);
+    if (base.mode != 1 || base.remap != 0 || logr < 3) {
+        *sequential = true;
+        return nullptr;
+    }
+    uint64_t key = mix64(0x5eed, (uint64_t)count);
+    key = mix64(key, (uint64_t)l);
+    key = hash_bytes(key, &base, sizeof(base));
+    for (int i = 0; i < count; ++i) {
+        key = mix64(key, (uint64_t)(uintptr_t)hs[i]->buf);
+        key = mix64(key, (uint64_t)hs[i]->n);
+        key = hash_bytes(key, hs[i]->l2p.data(), hs[i]->l2p.size() * sizeof(int));
+        key = hash_bytes(key, gates[i], m[i] * sizeof(sv_gate));
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        for (size_t k = 0; k < g_batches.size(); ++k)
+            if (g_batches[k]->key == key && g_batches[k]->count == count) {
+                BatchEntry *e = g_batches[k];
+                g_batches.erase(g_batches.begin() + k);
+                g_batches.push_back(e);
+                return e;
+            }
+    }
+    // plan every instance with the shared block size
+    std::vector<svp::Plan> plans(count);
+    for (int i = 0; i < count; ++i) {
+        svp::PlanConfig c = config_from(hs[i], s);
+        c.l = l;
+        c.logr = logr;
+        std::string e = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates[i]), m[i], hs[i]->l2p, plans[i]);
+        if (!e.empty()) {
+            *err = "instance " + std::to_string(i) + ": " + e;
+            return nullptr;
+        }
+        for (const svp::Step &st : plans[i].steps)
+            if (st.kind != svp::ST_K2) {
+                *sequential = true;
+                return nullptr;
+            }
+    }
+    // concatenate ops and tables, rebasing table offsets
+    std::vector<svp::K2Op> ops;
+    std::vector<uint8_t> table;
+    std::vector<svp::BatchPass> passes;
+    std::vector<svp::BatchInst> insts(count);
+    std::vector<double> work(count);
+    int max_nug = 0;
+    for (int i = 0; i < count; ++i) {
+        const svp::Plan &P = plans[i];
+        const size_t tb = align16(table.size());
+        table.resize(tb + P.table.size());
+        if (!P.table.empty()) std::memcpy(table.data() + tb, P.table.data(), P.table.size());
+        const int ob = (int)ops.size();
+        for (svp::K2Op op : P.ops) {
+            if (op.kind == svp::K2_DIAGRUN) {
+                op.a += (int)tb;
+                svp::DiagRec *rec = reinterpret_cast<svp::DiagRec *>(table.data() + op.a);
+                if (rec->has_group && rec->pad == 0) {
+                    if (rec->g.lane_off >= 0) rec->g.lane_off += (int)tb;
+                    if (rec->g.wave_off >= 0) rec->g.wave_off += (int)tb;
+                    rec->pad = 1;  // rebased
+                }
+            }
+            ops.push_back(op);
+        }
+        insts[i].S = hs[i]->buf;
+        insts[i].pass_off = (int)passes.size();
+        insts[i].npass = 0;
+        insts[i].ctr = i;
+        for (const svp::Step &st : P.steps) {
+            svp::BatchPass bp{};
+            bp.args.n = hs[i]->n;
+            bp.args.l = st.l;
+            bp.args.nops = st.op_count;
+            bp.args.nug = st.nug;
+            bp.args.ug_off = st.nug ? (int)(st.ug_off + tb) : 0;
+            bp.args.vec2 = (st.l >= 2 && st.logr >= 2 && st.bits[0] == 0) ? 1 : 0;
+            std::vector<bool> in(hs[i]->n, false);
+            for (int b = 0; b < st.l; ++b) {
+                bp.args.bits[b] = (int8_t)st.bits[b];
+                in[st.bits[b]] = true;
+            }
+            int k = 0;
+            for (int p = 0; p < hs[i]->n; ++p)
+                if (!in[p]) bp.args.nbits[k++] = (int8_t)p;
+            bp.op_begin = ob + st.op_begin;
+            if (st.nug) {
+                svp::UGroup *ug = reinterpret_cast<svp::UGroup *>(table.data() + bp.args.ug_off);
+                for (int g = 0; g < st.nug; ++g) ug[g].term_off += (int)tb;
+            }
+            max_nug = std::max(max_nug, st.nug);
+            passes.push_back(bp);
+            insts[i].npass += 1;
+        }
+        work[i] = (double)insts[i].npass * std::ldexp(1.0, hs[i]->n - l);
+    }
+    // resident capacity and work-group groups
+    const unsigned threads = 1u << (l - logr);
+    const size_t amp = dtype == 0 ? 8 : 16;
+    const size_t lds = (amp << l) + (size_t)max_nug * 16;
+    const int per_cu = svk::k6_occupancy(dtype, logr, threads, lds);
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1) {
+        *err = "cannot size the batch launch";
+        return nullptr;
+    }
+    const long cap = (long)per_cu * cus;
+    if (count > cap) {
+        *sequential = true;
+        return nullptr;
+    }
+    double wsum = 0;
+    for (double w : work) wsum += w;
+    std::vector<int> gsz(count);
+    long total = 0;
+    for (int i = 0; i < count; ++i) {
+        const double blocks = std::ldexp(1.0, hs[i]->n - l);
+        double g = std::floor((double)cap * work[i] / wsum);
+        g = std::max(1.0, std::min(g, blocks));
+        gsz[i] = (int)g;
+        total += gsz[i];
+    }
+    while (total > cap) {
+        int big = (int)(std::max_element(gsz.begin(), gsz.end()) - gsz.begin());
+        gsz[big] -= 1;
+        total -= 1;
+    }
+    std::vector<int32_t> wg_inst;
+    for (int i = 0; i < count; ++i) {
+        insts[i].group_off = (int)wg_inst.size();
+        insts[i].group_size = gsz[i];
+        for (int g = 0; g < gsz[i]; ++g) wg_inst.push_back(i);
+    }
+    // one device buffer: insts | wg_inst | passes | ops | table | counters
+    BatchEntry *e = new (std::nothrow) BatchEntry();
+    if (!e) {
+        *err = "host allocation failed";
+        return nullptr;
+    }
+    const size_t o_inst = 0, o_wg = align16(o_inst + insts.size() * sizeof(svp::BatchInst));
+    const size_t o_pass = align16(o_wg + wg_inst.size() * sizeof(int32_t));
+    const size_t o_ops = align16(o_pass + passes.size() * sizeof(svp::BatchPass));
+    const size_t o_tab = align16(o_ops + ops.size() * sizeof(svp::K2Op));
+    const size_t o_ctr = align16(o_tab + table.size());
+    const size_t bytes = o_ctr + (size_t)(count + 1) * sizeof(unsigned);
+    if (dev_alloc(&e->dbuf, bytes) != hipSuccess) {
+        delete e;
+        *err = "batch buffer allocation failed";
+        return nullptr;
+    }
+    char *d = static_cast<char *>(e->dbuf);
+    for (svp::BatchPass &bp : passes) bp.args.table = reinterpret_cast<const uint8_t *>(d + o_tab);
+    hipStream_t st = hs[0]->stream;
+    hipError_t he = hipSuccess;
+    auto up = [&](size_t off, const void *src, size_t n) {
+        if (he == hipSuccess && n) he = hipMemcpyAsync(d + off, src, n, hipMemcpyHostToDevice, st);
+    };
+    up(o_inst, insts.data(), insts.size() * sizeof(svp::BatchInst));
+    up(o_wg, wg_inst.data(), wg_inst.size() * sizeof(int32_t));
+    up(o_pass, passes.data(), passes.size() * sizeof(svp::BatchPass));
+    up(o_ops, ops.data(), ops.size() * sizeof(svp::K2Op));
+    up(o_tab, table.data(), table.size());
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    e->ctrs = reinterpret_cast<unsigned *>(d + o_ctr);
+    e->key = key;
+    e->dtype = dtype;
+    e->logr = logr;
+    e->count = count;
+    e->grid = (unsigned)wg_inst.size();
+    e->threads = threads;
+    e->lds = lds;
+    e->l = l;
+    for (int i = 0; i < count; ++i) {
+        e->l2p_after.push_back(plans[i].l2p_after);
+        e->stats.push_back(plans[i].stats);
+    }
+    // capture: clear counters and error flag with a kernel, then the batch
+    if (he == hipSuccess) he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+        hipError_t h1 = svk::zero_u32(e->ctrs, (uint32_t)(count + 1), st);
+        hipError_t h2 = svk::k6_batch(dtype, logr, e->grid, threads, lds,
+                                      reinterpret_cast<const svp::BatchInst *>(d + o_inst),
+                                      reinterpret_cast<const int32_t *>(d + o_wg),
+                                      reinterpret_cast<const svp::BatchPass *>(d + o_pass),
+                                      reinterpret_cast<const svp::K2Op *>(d + o_ops), e->ctrs,
+                                      reinterpret_cast<int *>(e->ctrs + count), 1u << 24, st);
+        he = hipStreamEndCapture(st, &e->graph);
+        if (he == hipSuccess) he = h1 != hipSuccess ? h1 : h2;
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+        *err = std::string("batch graph: ") + hipGetErrorString(he);
+        delete e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_batches.push_back(e);
+    while (g_batches.size() > 8) {
+        delete g_batches.front();
+        g_batches.erase(g_batches.begin());
+    }
+    return e;
+}
+
+sv_status check_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m)
+{
+    if (count < 0 || (count > 0 && (!hs || !gates || !m))) return fail(SV_ERR_INVALID_ARG, "bad batch arrays");
+    std::unordered_set<const void *> seen;
+    for (int i = 0; i < count; ++i) {
+        if (sv_status st = check_handle(hs[i])) return st;
+        if (!seen.insert(hs[i]).second) return fail(SV_ERR_INVALID_ARG, "a handle appears twice in the batch");
+        if (hs[i]->dtype != hs[0]->dtype) return fail(SV_ERR_INVALID_ARG, "mixed dtypes in one batch");
+        if (m[i] > 0 && !gates[i]) return fail(SV_ERR_INVALID_ARG, "null gate list");
+        std::string e = svp::validate(hs[i]->n, reinterpret_cast<const svp::RawGate *>(gates[i]), m[i]);
+        if (!e.empty()) return fail(SV_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": " + e);
+    }
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m,
+                         const sv_schedule *s)
+{
+    if (sv_status st = check_batch(hs, count, gates, m)) return st;
+    if (count == 0) return SV_OK;
+    if (sv_status st = check_schedule(s, hs[0]->dtype)) return st;
+    bool sequential = false;
+    std::string err;
+    BatchEntry *e = get_batch(hs, count, gates, m, s, &sequential, &err);
+    if (sequential) {
+        for (int i = 0; i < count; ++i)
+            if (sv_status st = sv_apply_circuit(hs[i], gates[i], m[i], s)) return st;
+        return SV_OK;
+    }
+    if (!e) return fail(SV_ERR_DEVICE, err);
+    if (!g_err_host) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, sizeof(int), 0) != hipSuccess) return fail(SV_ERR_OUT_OF_MEMORY, "pinned flag");
+        g_err_host = static_cast<int *>(p);
+    }
+    sv_handle h0 = hs[0];
+    hipStream_t st = h0->stream;
+    if (launch_fault()) return fail(SV_ERR_DEVICE, "injected launch failure");
+    SV_HIP(hipEventRecord(h0->ev0, st), "hipEventRecord");
+    SV_HIP(hipGraphLaunch(e->exec, st), "hipGraphLaunch");
+    SV_HIP(hipEventRecord(h0->ev1, st), "hipEventRecord");
+    SV_HIP(hipMemcpyAsync(g_err_host, e->ctrs + count, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+    SV_HIP(hipStreamSynchronize(st), "sync");
+    if (*g_err_host != 0) return fail(SV_ERR_DEVICE, "batch pass barrier did not complete (timed out)");
+    float ms = 0.f;
+    SV_HIP(hipEventElapsedTime(&ms, h0->ev0, h0->ev1), "hipEventElapsedTime");
+    for (int i = 0; i < count; ++i) {
+        sv_handle h = hs[i];
+        h->l2p = e->l2p_after[i];
+        std::memset(&h->st, 0, sizeof(h->st));
+        h->st.gates = e->stats[i].gates;
+        h->st.swaps = e->stats[i].swaps;
+        h->st.phases = e->stats[i].phases;
+        h->st.passes = e->stats[i].passes;
+        h->st.bytes = e->stats[i].bytes;
+        h->st.device_ms = ms;
+        h->st.block_qubits = e->l;
+        h->st.mode = 1;
+        h->st.fuse_k = s ? s->fuse_k : 1;
+        h->st.swap_policy = s ? s->swap_policy : SV_SWAP_LOOKAHEAD;
+        h->timed = false;
+    }
+    return SV_OK;
+}
+
+sv_status sv_tune_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m, sv_schedule *out)
+{
+    if (sv_status st = check_batch(hs, count, gates, m)) return st;
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    if (count == 0) return fail(SV_ERR_INVALID_ARG, "empty batch");
+    const int dtype = hs[0]->dtype;
+    int min_n = 64;
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        min_n = std::min(min_n, hs[i]->n);
+        total += align16(hs[i]->bytes);
+    }
+    // scratch copies of every state, wrapped in temporary handles
+    void *scratch = nullptr;
+    if (dev_alloc(&scratch, total) != hipSuccess) return fail(SV_ERR_OUT_OF_MEMORY, "tuner scratch");
+    std::vector<sv_handle> tmp(count, nullptr);
+    sv_status rc = SV_OK;
+    size_t off = 0;
+    for (int i = 0; i < count && rc == SV_OK; ++i) {
+        char *dst = static_cast<char *>(scratch) + off;
+        off += align16(hs[i]->bytes);
+        const size_t nb = amp_bytes(dtype) << hs[i]->n;
+        if (hipMemcpyAsync(dst, hs[i]->buf, nb, hipMemcpyDeviceToDevice, hs[0]->stream) != hipSuccess) rc = SV_ERR_DEVICE;
+        else rc = sv_wrap(hs[i]->n, (sv_dtype)dtype, dst, nb, hs[0]->stream, &tmp[i]);
+        if (rc == SV_OK) tmp[i]->l2p = hs[i]->l2p;
+    }
+    sv_schedule best{};
+    double best_ms = 1e30;
+    if (rc == SV_OK) {
+        const int lmax = std::min(min_n, svp::max_block_qubits(dtype));
+        for (int l = std::max(7, lmax - 3); l <= lmax && rc == SV_OK; ++l)
+            for (int fuse = 0; fuse <= 1 && rc == SV_OK; ++fuse) {
+                sv_schedule c{};
+                c.mode = SV_PARTITIONED;
+                c.block_qubits = l;
+                c.fuse_k = fuse;
+                c.swap_policy = SV_SWAP_LOOKAHEAD;
+                c.remap = SV_REMAP_VIRTUAL;
+                c.diag_free = 1;
+                std::vector<double> t;
+                for (int rep = 0; rep < 4 && rc == SV_OK; ++rep) {
+                    rc = sv_apply_batch(tmp.data(), count, gates, m, &c);
+                    if (rc == SV_OK && rep > 0) t.push_back(tmp[0]->st.device_ms);
+                }
+                if (rc != SV_OK) break;
+                std::sort(t.begin(), t.end());
+                const double med = t[t.size() / 2];
+                if (med < best_ms) {
+                    best_ms = med;
+                    best = c;
+                }
+            }
+    }
+    for (sv_handle h : tmp)
+        if (h) sv_destroy(h);
+    hipStreamSynchronize(hs[0]->stream);
+    hipFree(scratch);
+    if (rc != SV_OK) return rc;
+    *out = best;
+    return SV_OK;
 }
 
 }  // extern "C"

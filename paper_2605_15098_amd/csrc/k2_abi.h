@@ -91,4 +91,22 @@ struct K2Args {
     int8_t nbits[48];          // memory bits outside the block, ascending
 };
 
+// Batched passes (one persistent launch over many states). Instance i is
+// served by work-groups group_off .. group_off + group_size - 1, which run its
+// passes in order and meet at a counter barrier between passes.
+struct BatchInst {
+    void *S;             // the instance's state
+    int32_t npass;
+    int32_t pass_off;    // first BatchPass of this instance
+    int32_t group_off;   // first work-group
+    int32_t group_size;  // work-groups sharing the instance
+    int32_t ctr;         // barrier counter index
+    int32_t pad;
+};
+struct BatchPass {
+    K2Args args;         // args.table points to the batch table
+    int32_t op_begin;    // first op in the batch op array
+    int32_t pad[3];
+};
+
 }  // namespace svp

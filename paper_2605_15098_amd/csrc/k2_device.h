@@ -369,8 +369,8 @@ __device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t
     }
 }
 
-// Block-resident pass, persistent: work-group w handles blocks w, w + G, ...
-// (G = grid size) and loads block i+1 into registers while it runs the
+// Block-resident pass, persistent: a work-group handles blocks first,
+// first + stride, ... and loads the next one into registers while it runs the
 // program on block i. A block is 2^l amplitudes: local bit i is memory bit
 // args.bits[i]; the other memory bits come from the block number. Each thread
 // holds R = 2^LOGR amplitudes in registers; register slot j stands for local
@@ -381,7 +381,7 @@ __device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t
 // access. lds must hold 2^l amplitudes followed by args.nug double2.
 template <typename T, int LOGR, class Prog>
 __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
-                                        unsigned char *lds, const Prog &prog)
+                                        unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
 {
     using C = typename CT<T>::type;
     constexpr int R = 1 << LOGR;
@@ -400,13 +400,14 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
 #pragma unroll
     for (int j = 1; j < LOGR; ++j) roff[j] = 1ull << args.bits[tb + j];
 
-    uint64_t bid = blockIdx.x;
+    uint64_t bid = first;
+    if (bid >= nblocks) return;
     uint64_t base = k2_base(bid, args);
     C a[R], b[R];
     k2_load<LOGR>(a, S, base | tmem_local, roff, vec2);
 
     for (;;) {
-        const uint64_t next = bid + gridDim.x;
+        const uint64_t next = bid + stride;
         const bool has_next = next < nblocks;
         const uint64_t nbase = has_next ? k2_base(next, args) : 0ull;
         if (has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);

@@ -194,7 +194,114 @@ __global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
 k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, svp::K2Args args)
 {
     extern __shared__ unsigned char lds_raw[];
-    k2_body<T, LOGR>(S, args, lds_raw, K2Interp{ops, args.nops, args.l});
+    k2_body<T, LOGR>(S, args, lds_raw, K2Interp{ops, args.nops, args.l}, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------- k6
+
+// Barrier of the work-groups that share one instance. Thread 0 releases the
+// group's stores device-wide, counts itself in, and waits (bounded) until the
+// count reaches `target`; a wait that exceeds `limit` polls, or an error
+// raised by another group, sets *err and makes every waiter leave, so the
+// grid always drains.
+__device__ bool group_barrier(unsigned *ctr, unsigned target, int *err, unsigned limit, int *ok)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(ctr, 1u);
+        unsigned spins = 0;
+        int good = 1;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                atomicExch(err, 1);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        __threadfence();
+        *ok = good;
+    }
+    __syncthreads();
+    return *ok != 0;
+}
+
+// Many states in one persistent launch: each work-group serves one instance
+// (wg_inst), runs every pass of that instance's program on its share of the
+// blocks, and waits for the instance's other work-groups between passes.
+template <typename T, int LOGR>
+__global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
+k6_batch_kernel(const svp::BatchInst *__restrict__ insts, const int32_t *__restrict__ wg_inst,
+                const svp::BatchPass *__restrict__ passes, const svp::K2Op *__restrict__ ops, unsigned *ctrs,
+                int *err, unsigned limit)
+{
+    using C = typename CT<T>::type;
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ int ok;
+    const svp::BatchInst I = insts[wg_inst[blockIdx.x]];
+    const uint64_t rank = blockIdx.x - I.group_off;
+    for (int p = 0; p < I.npass; ++p) {
+        const svp::BatchPass &P = passes[I.pass_off + p];
+        k2_body<T, LOGR>((C *)I.S, P.args, lds_raw, K2Interp{ops + P.op_begin, P.args.nops, P.args.l}, rank,
+                         (uint64_t)I.group_size);
+        if (I.group_size > 1 && p + 1 < I.npass)
+            if (!group_barrier(&ctrs[I.ctr], (unsigned)((p + 1) * I.group_size), err, limit, &ok)) return;
+    }
+}
+
+__global__ void __launch_bounds__(256) zero_u32_kernel(unsigned *p, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+hipError_t zero_u32(unsigned *p, uint32_t n, hipStream_t st)
+{
+    zero_u32_kernel<<<grid_for(n, 256, 1024), 256, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+static const void *k6_fn(int logr)
+{
+    switch (logr) {
+    case 3: return (const void *)k6_batch_kernel<T, 3>;
+    case 4: return (const void *)k6_batch_kernel<T, 4>;
+    default: return nullptr;
+    }
+}
+
+int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds)
+{
+    const void *fn = dtype == 0 ? k6_fn<float>(logr) : k6_fn<double>(logr);
+    if (!fn) return 0;
+    if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)threads, lds) != hipSuccess) return 0;
+    return per_cu;
+}
+
+hipError_t k6_batch(int dtype, int logr, unsigned grid, unsigned threads, size_t lds, const svp::BatchInst *insts,
+                    const int32_t *wg_inst, const svp::BatchPass *passes, const svp::K2Op *ops, unsigned *ctrs,
+                    int *err, unsigned limit, hipStream_t st)
+{
+    if (dtype == 0) {
+        if (logr == 3)
+            k6_batch_kernel<float, 3><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
+        else if (logr == 4)
+            k6_batch_kernel<float, 4><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        if (logr == 3)
+            k6_batch_kernel<double, 3><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
+        else if (logr == 4)
+            k6_batch_kernel<double, 4><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
+        else
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int LOGR>
@@ -308,10 +415,13 @@ hipError_t probabilities(const void *S, int n, int dtype, const int *perm, doubl
 struct BitList {
     int8_t b[48];
     int cnt;
+    int low;  // 1: b[k] == k + first (the bits form one contiguous run), first = b[0]
 };
 
+// Place bit k of v at position bl.b[k]. A contiguous run is one shift.
 __device__ __forceinline__ uint64_t deposit(uint64_t v, const BitList &bl)
 {
+    if (bl.low) return bl.cnt ? (v << bl.b[0]) : 0ull;
     uint64_t r = 0;
     for (int k = 0; k < bl.cnt; ++k) r |= ((v >> k) & 1ull) << bl.b[k];
     return r;
@@ -373,7 +483,11 @@ static BitList make_bits(const int *b, int cnt)
 {
     BitList bl{};
     bl.cnt = cnt;
-    for (int k = 0; k < cnt; ++k) bl.b[k] = (int8_t)b[k];
+    bl.low = 1;
+    for (int k = 0; k < cnt; ++k) {
+        bl.b[k] = (int8_t)b[k];
+        if (b[k] != b[0] + k) bl.low = 0;
+    }
     return bl;
 }
 
@@ -414,7 +528,7 @@ __device__ __forceinline__ bool better(double v1, uint64_t i1, double v2, uint64
     return v1 > v2 || (v1 == v2 && i1 < i2);
 }
 
-constexpr int AM_BLOCKS = 1024;
+constexpr int AM_BLOCKS = 8192;
 
 __device__ void block_argmax(double v, uint64_t i, double *rv, uint64_t *ri, double *outv, uint64_t *outi)
 {

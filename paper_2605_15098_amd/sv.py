@@ -96,6 +96,8 @@ _SIGS = {
     "sv_prepare": ([_VP, _VP, ctypes.c_size_t, ctypes.POINTER(sv_schedule), ctypes.c_int], ctypes.c_int32),
     "sv_apply_batch": ([ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP),
                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(sv_schedule)], ctypes.c_int32),
+    "sv_tune_batch": ([ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP),
+                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(sv_schedule)], ctypes.c_int32),
     "sv_probabilities": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _VP], ctypes.c_int32),
     "sv_state": ([_VP, _VP], ctypes.c_int32),
     "sv_state_range": ([_VP, ctypes.c_uint64, ctypes.c_uint64, _VP], ctypes.c_int32),
@@ -211,6 +213,16 @@ def sv_apply_batch(handles: Sequence[int], gate_lists: Sequence[np.ndarray],
     ps = (_VP * len(gl))(*[_VP(g.ctypes.data) for g in gl])
     ms = (ctypes.c_size_t * len(gl))(*[len(g) for g in gl])
     _check(load().sv_apply_batch(hs, len(handles), ps, ms, _sched_ptr(sched)))
+
+
+def sv_tune_batch(handles: Sequence[int], gate_lists: Sequence[np.ndarray]) -> sv_schedule:
+    gl = [_gates(g) for g in gate_lists]
+    hs = (_VP * len(handles))(*[_VP(h) for h in handles])
+    ps = (_VP * len(gl))(*[_VP(g.ctypes.data) for g in gl])
+    ms = (ctypes.c_size_t * len(gl))(*[len(g) for g in gl])
+    out = sv_schedule()
+    _check(load().sv_tune_batch(hs, len(handles), ps, ms, ctypes.byref(out)))
+    return out
 
 
 def sv_probabilities(h, qubits: Optional[Sequence[int]] = None, n: Optional[int] = None,

@@ -1,0 +1,127 @@
+"""Batched application (one persistent launch under a captured HIP graph).
+
+Each instance in a batch is planned like sv_apply_circuit with the batch's
+block size and runs the same pass handlers, so batch results must equal the
+one-at-a-time results bit for bit; QPE instances must also match the closed
+form (complex64 <= 2e-5, complex128 <= 1e-12) with the exact argmax.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import qpe as cf
+from paper_2605_15098_amd import sv
+from paper_2605_15098_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = {"c128": 1e-12, "c64": 2e-5}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make(ns, dtype):
+    return [sv.StateVector(n, dtype) for n in ns]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_qpe_matches_single_and_closed_form(dtype):
+    rng = np.random.default_rng(44)
+    ns = [9, 10, 12, 14, 15, 16, 11, 13]
+    phis = [float(x) for x in rng.random(len(ns))]
+    gl = [W.qpe_gates(n, p) for n, p in zip(ns, phis)]
+    l = 9
+    batch = make(ns, dtype)
+    log(f"case batch qpe dtype={dtype}")
+    sv.sv_apply_batch([s.h for s in batch], gl, sv.schedule(block_qubits=l))
+    for i, (n, p) in enumerate(zip(ns, phis)):
+        single = sv.StateVector(n, dtype)
+        single.apply(gl[i], sv.schedule(block_qubits=l))
+        a, b = batch[i].state(), single.state()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (i, n)
+        assert np.max(np.abs(a - cf.qpe_state(n, p))) <= TOL[dtype]
+        m, _, _ = batch[i].qpe_readout()
+        assert m == cf.qpe_argmax(n - 1, p)
+        single.close()
+    for s in batch:
+        s.close()
+
+
+def test_batch_replay_accumulates_and_random_circuits():
+    rng = np.random.default_rng(45)
+    ns = [10, 12, 13, 13, 15]
+    gl = [W.random_mixed_circuit(n, 60, rng, with_swap=True) for n in ns]
+    batch = make(ns, "c128")
+    ref = make(ns, "c128")
+    sched = sv.schedule(block_qubits=10)
+    for rep in range(3):  # the second call of each layout replays a cached graph
+        log(f"case batch replay {rep}")
+        sv.sv_apply_batch([s.h for s in batch], gl, sched)
+        for s, g in zip(ref, gl):
+            s.apply(g, sched)
+    for a, b in zip(batch, ref):
+        x, y = a.state(), b.state()
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+        assert a.layout() == b.layout()
+    for s in batch + ref:
+        s.close()
+
+
+def test_batch_tuner_leaves_states():
+    ns = [12, 13, 14]
+    gl = [W.qpe_gates(n, 0.3) for n in ns]
+    batch = make(ns, "c64")
+    before = [s.state() for s in batch]
+    log("case batch tuner")
+    best = sv.sv_tune_batch([s.h for s in batch], gl)
+    assert best.mode == sv.SV_PARTITIONED and 7 <= best.block_qubits <= 12
+    for s, b in zip(batch, before):
+        assert np.array_equal(s.state(), b)
+    sv.sv_apply_batch([s.h for s in batch], gl, best)
+    for s, n in zip(batch, ns):
+        assert np.max(np.abs(s.state() - cf.qpe_state(n, 0.3))) <= 2e-5
+    for s in batch:
+        s.close()
+
+
+def test_batch_errors():
+    a = sv.StateVector(8, "c64")
+    b = sv.StateVector(8, "c128")
+    g = W.qpe_gates(8, 0.1)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_apply_batch([a.h, b.h], [g, g])
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
+    with pytest.raises(sv.SvError):
+        sv.sv_apply_batch([a.h, a.h], [g, g])
+    bad = W.gates_from_tuples([("H", 9, -1, 0.0)])
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_apply_batch([a.h], [bad])
+    assert "instance 0" in e.value.message
+    a.close()
+    b.close()
+
+
+def test_batch_256_instances_config():
+    """256 QPE instances, 12..22 qubits, complex64, as in the batched workload."""
+    inst = W.batch_instances(256, seed=4)
+    gl = [W.qpe_gates(n, p) for n, p in inst]
+    batch = [sv.StateVector(n, "c64") for n, _ in inst]
+    log("case batch 256")
+    sv.sv_apply_batch([s.h for s in batch], gl, sv.schedule(block_qubits=12))
+    worst = 0.0
+    rng = np.random.default_rng(7)
+    for s, (n, p) in zip(batch, inst):
+        t = n - 1
+        m, _, _ = s.qpe_readout()
+        assert m == cf.qpe_argmax(t, p)
+        k0 = max(0, min((1 << t) - 512, cf.qpe_argmax(t, p) - 256))
+        starts = [k0, int(rng.integers(0, (1 << t) - 512))]
+        for a in starts:
+            got = sv.sv_state_range(s.h, (1 << t) + a, 512, "c64").astype(np.complex128)
+            worst = max(worst, float(np.max(np.abs(got - cf.qpe_amplitudes(t, p, np.arange(a, a + 512))))))
+    assert worst <= 2e-5, worst
+    for s in batch:
+        s.close()
