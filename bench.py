@@ -141,6 +141,56 @@ def cpu_baseline(n_target, phi, budget_s=20.0):
                       f"(complex128) Algorithm 1 on the host, {el:.1f} s"}
 
 
+def bench_batch(steps):
+    """256 QPE instances (12..22 qubits, complex64) in one persistent launch
+    under a captured graph, schedule picked by the batch autotuner."""
+    import torch
+    from oracle import qpe as cf
+    from paper_2605_15098_amd import sv
+    from paper_2605_15098_amd import workloads as W
+
+    inst = W.batch_instances(256, seed=4)
+    gl = [W.qpe_gates(n, p) for n, p in inst]
+    states = [sv.StateVector(n, "c64") for n, _ in inst]
+    hs = [s.h for s in states]
+    t0 = time.perf_counter()
+    best = sv.sv_tune_batch(hs, gl)
+    tune_s = time.perf_counter() - t0
+    log(f"batch tuner: block_qubits={best.block_qubits} fuse_k={best.fuse_k} ({tune_s:.1f} s)")
+    for _ in range(2):
+        sv.sv_apply_batch(hs, gl, best)
+    torch.cuda.synchronize()
+    dev = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sv.sv_apply_batch(hs, gl, best)
+        dev.append(states[0].stats()["device_ms"])
+    wall = (time.perf_counter() - t0) / steps
+    # correctness: every instance from |0>, argmax and sampled amplitudes
+    for s in states:
+        s.reset()
+    sv.sv_apply_batch(hs, gl, best)
+    worst, argmax_ok = 0.0, 0
+    rng = np.random.default_rng(99)
+    for s, (n, p) in zip(states, inst):
+        t = n - 1
+        m, _, _ = s.qpe_readout()
+        argmax_ok += int(m == cf.qpe_argmax(t, p))
+        for a in (max(0, min((1 << t) - 256, cf.qpe_argmax(t, p) - 128)), int(rng.integers(0, (1 << t) - 256))):
+            got = sv.sv_state_range(s.h, (1 << t) + a, 256, "c64").astype(np.complex128)
+            worst = max(worst, float(np.max(np.abs(got - cf.qpe_amplitudes(t, p, np.arange(a, a + 256))))))
+    for s in states:
+        s.close()
+    torch.cuda.empty_cache()
+    res = {"instances": len(inst), "qubits": [min(n for n, _ in inst), max(n for n, _ in inst)],
+           "instances_per_s": len(inst) / wall, "ms_per_batch": 1000 * wall,
+           "device_ms_per_batch": float(np.median(dev)), "schedule": {"block_qubits": best.block_qubits,
+                                                                        "fuse_k": best.fuse_k},
+           "tuning_s": tune_s, "max_abs_err_sampled": worst, "argmax_exact": f"{argmax_ok}/{len(inst)}"}
+    log(f"batch: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +295,8 @@ def main():
             torch.cuda.empty_cache()
         out["comparisons"] = comps
         out["speedup_vs_c128_plain"] = value / comps["c128-plain"]["gate_sweeps_per_s"]
+    if not args.quick:
+        out["batch_qpe256"] = bench_batch(args.steps)
     if not args.quick and not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(n, phi)

@@ -991,19 +991,24 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
         e->l2p_after.push_back(plans[i].l2p_after);
         e->stats.push_back(plans[i].stats);
     }
-    // capture: clear counters and error flag with a kernel, then the batch
-    if (he == hipSuccess) he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    // capture on a private stream (the handle's stream may be the legacy
+    // default stream, which cannot be captured); the graph is then launched on
+    // the handle's stream. Counters and the error flag are cleared by a kernel.
+    hipStream_t cap_st = nullptr;
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
-        hipError_t h1 = svk::zero_u32(e->ctrs, (uint32_t)(count + 1), st);
+        hipError_t h1 = svk::zero_u32(e->ctrs, (uint32_t)(count + 1), cap_st);
         hipError_t h2 = svk::k6_batch(dtype, logr, e->grid, threads, lds,
                                       reinterpret_cast<const svp::BatchInst *>(d + o_inst),
                                       reinterpret_cast<const int32_t *>(d + o_wg),
                                       reinterpret_cast<const svp::BatchPass *>(d + o_pass),
                                       reinterpret_cast<const svp::K2Op *>(d + o_ops), e->ctrs,
-                                      reinterpret_cast<int *>(e->ctrs + count), 1u << 24, st);
-        he = hipStreamEndCapture(st, &e->graph);
+                                      reinterpret_cast<int *>(e->ctrs + count), 1u << 24, cap_st);
+        he = hipStreamEndCapture(cap_st, &e->graph);
         if (he == hipSuccess) he = h1 != hipSuccess ? h1 : h2;
     }
+    if (cap_st) hipStreamDestroy(cap_st);
     if (he == hipSuccess) he = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
     if (he != hipSuccess) {
         *err = std::string("batch graph: ") + hipGetErrorString(he);
