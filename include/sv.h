@@ -108,8 +108,10 @@ typedef struct {
     int32_t diag_free;    /* 0: every gate's target must be local (the paper's
                              rule); 1: diagonal gates (Z, P, RZ and their
                              controlled forms) never force a SWAP              */
-    int32_t tuner;        /* SV_TUNER_*: sv_apply_circuit first picks l, k and
-                             the policy itself                                */
+    int32_t tuner;        /* SV_TUNER_*: sv_apply_circuit first picks the
+                             schedule itself (sv_tune); NONE = use this one   */
+    int32_t reg_qubits;   /* amplitudes per thread in a block pass = 2^this;
+                             0 = default (4)                                  */
 } sv_schedule;
 
 typedef struct {
@@ -228,11 +230,87 @@ sv_status sv_stats_get(sv_handle h, sv_stats *out);
 sv_status sv_plan(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const sv_schedule *s,
                   sv_stats *out);
 
-/* Pick a schedule for this circuit on this handle. mode = SV_TUNER_EXHAUSTIVE
- * times every candidate on a scratch copy of the state; SV_TUNER_LEARNED asks
- * the cost model loaded by sv_model_load (falls back to exhaustive without
- * one). The state itself is not changed. */
+/* ---- schedule tuning (the paper sweeps the block size by hand over a
+ * range and keeps the median of three runs, Section IV-B) ----
+ *
+ * Candidates: partitioned schedules with virtual remap, diagonal gates free
+ * and diagonal runs combined (fuse_k 1), over
+ *   block qubits  the three largest sizes that fit on chip (complex64 11..13,
+ *                 complex128 10..12; capped at n),
+ *   register tile 2^4 or 2^5 amplitudes per thread (complex64),
+ *                 2^3 or 2^4 (complex128),
+ *   swap placement look-ahead bulk remap or LRU
+ * (a block smaller than the register tile is one tile). sv_tune_candidates
+ * writes up to cap of them to out (out may be NULL) and their number to
+ * *count (12 when n is at least the largest size). */
+sv_status sv_tune_candidates(int n, sv_dtype dtype, sv_schedule *out, int cap, int *count);
+
+/* Pick a schedule for this circuit on this handle among the candidates.
+ * mode = SV_TUNER_EXHAUSTIVE times every candidate on a scratch copy of the
+ * state (median of three timed runs after one warm-up, device time) and
+ * returns the fastest; SV_TUNER_LEARNED ranks them with the cost model set by
+ * sv_set_cost_model, one forward pass of the network on the device over all
+ * candidates, and returns the smallest prediction (exhaustive when no model
+ * is set). The state and its layout are not changed. OUT_OF_MEMORY if the
+ * scratch copy does not fit (exhaustive only). out->tuner is SV_TUNER_NONE. */
 sv_status sv_tune(sv_handle h, const sv_gate *gates, size_t m, int mode, sv_schedule *out);
+
+/* Device time in ms of each of ncand schedules for this circuit on this
+ * handle, measured as sv_tune(EXHAUSTIVE) measures it (repeats timed runs
+ * after one warm-up, median) on a scratch copy; ms_out[i] for cands[i]. Also
+ * returns, in compile_ms (may be NULL), the host time spent compiling each
+ * candidate's pass kernels (0 when they were cached). */
+sv_status sv_tune_time(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *cands, int ncand,
+                       int repeats, double *ms_out, double *compile_ms);
+
+/* Compile the pass kernels of this circuit under schedule s for an n-qubit
+ * state in the identity layout, without touching a device: the result lands
+ * in the run-time compiler's on-disk cache, where later calls on a device
+ * find it. For worker processes that compile ahead of a timed run. */
+sv_status sv_jit_precompile(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const sv_schedule *s);
+
+/* Features of (circuit, schedule) for the cost model, from host-side
+ * planning of an n-qubit state in the identity layout (no device work).
+ * out receives SV_FEATURES floats:
+ *   0 n                        8 explicit swap passes
+ *   1 bytes per amplitude      9 plain sweeps
+ *   2 block qubits l          10 log2 of the algorithmic bytes of all passes
+ *   3 register qubits         11 device ops over all block passes
+ *   4 swap policy (1 = LA)    12 most ops in one block pass
+ *   5 fuse_k                  13 dense ops (H, X, 2x2)
+ *   6 non-SWAP gates          14 diagonal ops (phase, diag, diagonal run)
+ *   7 block passes            15 layout ops (register/LDS re-layouts) */
+#define SV_FEATURES 16
+sv_status sv_features(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const sv_schedule *s, float *out);
+
+/* ---- the cost model network (k7): in -> 64 -> 64 -> 1, ReLU, FP32 ----
+ * Parameters are one flat float array: W1[64][in], b1[64], W2[64][64],
+ * b2[64], w3[64], b3 (sv_mlp_param_count(in) floats). Inputs are standardised
+ * in the kernels with norm = {mean[in], inv_std[in]} (NULL: identity).
+ * All pointers below are DEVICE pointers; work is enqueued on stream (a
+ * hipStream_t, NULL = the null stream) and is stream-ordered. in must be in
+ * [1, 32], batch >= 1; otherwise INVALID_ARG. */
+#define SV_MLP_HIDDEN 64
+size_t sv_mlp_param_count(int in);
+/* y[s] = prediction for row s of x (batch x in, row-major). */
+sv_status sv_mlp_forward(const float *params, int in, const float *norm, const float *x, int batch, float *y,
+                         void *stream);
+/* Bytes of device workspace sv_mlp_grad needs for this batch. */
+size_t sv_mlp_workspace_bytes(int in, int batch);
+/* grad = gradient of L = mean_s (y_s - target_s)^2 with respect to params;
+ * *loss = L (device float; loss may be NULL). Deterministic. */
+sv_status sv_mlp_grad(const float *params, int in, const float *norm, const float *x, const float *target,
+                      int batch, float *grad, float *loss, void *workspace, void *stream);
+/* One Adam step (bias-corrected; step counts from 1) on count parameters
+ * with first and second moments m, v (updated in place). */
+sv_status sv_mlp_adam(float *params, float *m, float *v, const float *grad, size_t count, float lr,
+                      float beta1, float beta2, float eps, int step, void *stream);
+
+/* Install the cost model used by sv_tune(SV_TUNER_LEARNED): HOST arrays of
+ * sv_mlp_param_count(in) parameters and 2*in normalisation floats (NULL:
+ * identity); in must be SV_FEATURES. The library keeps copies; params NULL
+ * removes the model. Process-wide. */
+sv_status sv_set_cost_model(const float *params, int in, const float *norm);
 
 /* Record a HIP event pair around every kernel of later sv_apply_circuit
  * calls on this handle (on = 1) so sv_stats_get reports per-kernel device

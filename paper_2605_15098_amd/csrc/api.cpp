@@ -17,6 +17,7 @@
 #include "../../include/sv.h"
 #include "jit.h"
 #include "launch.h"
+#include "mlp.h"
 #include "plan.h"
 
 namespace {
@@ -195,6 +196,7 @@ svp::PlanConfig config_from(sv_handle h, const sv_schedule *s)
         c.remap = s->remap;
         c.diag_free = s->diag_free;
         c.fuse_k = s->fuse_k;
+        if (s->reg_qubits > 0) c.logr = s->reg_qubits;
     }
     if (const char *e = std::getenv("SV_PIN_BITS")) c.pin_low = std::atoi(e);
     if (const char *e = std::getenv("SV_LOGR")) c.logr = std::atoi(e);
@@ -216,7 +218,11 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
     if (s->fuse_k > 6) return fail(SV_ERR_UNSUPPORTED, "fuse_k above 6");
     if (s->fuse_k > 1) return fail(SV_ERR_UNSUPPORTED, "dense fusion is not available in this build");
     if (s->outer_qubits != 0) return fail(SV_ERR_UNSUPPORTED, "outer tier is not available in this build");
-    if (s->tuner != SV_TUNER_NONE) return fail(SV_ERR_UNSUPPORTED, "tuner inside apply is not available");
+    if (s->tuner != SV_TUNER_NONE && s->tuner != SV_TUNER_EXHAUSTIVE && s->tuner != SV_TUNER_LEARNED)
+        return fail(SV_ERR_INVALID_ARG, "unknown tuner");
+    if (s->reg_qubits < 0) return fail(SV_ERR_INVALID_ARG, "reg_qubits < 0");
+    if (s->reg_qubits > (dtype == SV_COMPLEX64 ? 5 : 4))
+        return fail(SV_ERR_UNSUPPORTED, "reg_qubits above the register budget for this dtype");
     return SV_OK;
 }
 
@@ -485,6 +491,11 @@ sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv
 {
     if (sv_status st = check_handle(h)) return st;
     if (sv_status st = check_schedule(s, h->dtype)) return st;
+    sv_schedule tuned;
+    if (s && s->tuner != SV_TUNER_NONE) {
+        if (sv_status st = sv_tune(h, gates, m, s->tuner, &tuned)) return st;
+        s = &tuned;
+    }
     const auto t0 = std::chrono::steady_clock::now();
     svp::PlanConfig c = config_from(h, s);
     svp::Plan plan;
@@ -736,14 +747,329 @@ sv_status sv_set_state_range(sv_handle h, uint64_t offset, uint64_t count, const
     return state_io(h, offset, count, nullptr, in);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ tuning
+
+namespace {
+
+struct CostModel {
+    int in = 0;
+    std::vector<float> params, norm;
+};
+std::mutex g_model_mu;
+CostModel g_model;
+
+std::vector<sv_schedule> candidates(int n, int dtype)
+{
+    std::vector<sv_schedule> out;
+    const int top = std::min(n, svp::default_block_qubits(dtype));
+    const int r0 = dtype == SV_COMPLEX64 ? 4 : 3;
+    for (int l = std::max(1, top - 2); l <= top; ++l)
+        for (int r = r0; r <= r0 + 1; ++r) {
+            if (r > l && r != r0) continue;  // small blocks: one tile of 2^l
+            for (int pol : {SV_SWAP_LOOKAHEAD, SV_SWAP_LRU}) {
+                sv_schedule c{};
+                c.mode = SV_PARTITIONED;
+                c.block_qubits = l;
+                c.fuse_k = 1;
+                c.swap_policy = pol;
+                c.remap = SV_REMAP_VIRTUAL;
+                c.diag_free = 1;
+                c.reg_qubits = std::min(r, l);
+                out.push_back(c);
+            }
+        }
+    return out;
+}
+
+svp::PlanConfig config_for(int n, int dtype, const sv_schedule *s)
+{
+    sv_handle_s tmp;
+    tmp.n = n;
+    tmp.dtype = dtype;
+    return config_from(&tmp, s);
+}
+
+void plan_features(int n, int dtype, const svp::PlanConfig &c, const svp::Plan &p, float *f)
+{
+    double k2 = 0, k3 = 0, k1 = 0, ops = 0, maxops = 0, dense = 0, diag = 0, layout = 0;
+    int logr = 0;
+    for (const svp::Step &st : p.steps) {
+        if (st.kind == svp::ST_K1) k1 += 1;
+        else if (st.kind == svp::ST_K3) k3 += 1;
+        else {
+            k2 += 1;
+            logr = st.logr;
+            ops += st.op_count;
+            maxops = std::max(maxops, (double)st.op_count);
+            for (int i = 0; i < st.op_count; ++i) {
+                const int kind = p.ops[st.op_begin + i].kind;
+                if (kind == svp::K2_DENSE || kind == svp::K2_H || kind == svp::K2_X || kind == svp::K2_HU) dense += 1;
+                else if (kind == svp::K2_PHASE || kind == svp::K2_DIAG || kind == svp::K2_DIAGRUN) diag += 1;
+                else if (kind == svp::K2_LAYOUT) layout += 1;
+            }
+        }
+    }
+    f[0] = (float)n;
+    f[1] = (float)amp_bytes(dtype);
+    f[2] = (float)(c.mode == 1 ? p.l : 0);
+    f[3] = (float)logr;
+    f[4] = (float)(c.policy == SV_SWAP_LOOKAHEAD ? 1 : 0);
+    f[5] = (float)c.fuse_k;
+    f[6] = (float)p.stats.gates;
+    f[7] = (float)k2;
+    f[8] = (float)k3;
+    f[9] = (float)k1;
+    f[10] = (float)std::log2(std::max(1.0, p.stats.bytes));
+    f[11] = (float)ops;
+    f[12] = (float)maxops;
+    f[13] = (float)dense;
+    f[14] = (float)diag;
+    f[15] = (float)layout;
+}
+
+sv_status status_of(hipError_t e, const char *what)
+{
+    return e == hipSuccess ? SV_OK : hip_fail(e, what);
+}
+
+}  // namespace
+
+extern "C" {
+
+sv_status sv_tune_candidates(int n, sv_dtype dtype, sv_schedule *out, int cap, int *count)
+{
+    if (n < 1 || n > 36) return fail(SV_ERR_INVALID_ARG, "n must be in [1, 36]");
+    if (dtype != SV_COMPLEX64 && dtype != SV_COMPLEX128) return fail(SV_ERR_INVALID_ARG, "unknown dtype");
+    if (!count) return fail(SV_ERR_INVALID_ARG, "count is null");
+    if (cap < 0) return fail(SV_ERR_INVALID_ARG, "cap < 0");
+    const std::vector<sv_schedule> c = candidates(n, dtype);
+    if (out)
+        for (int i = 0; i < (int)c.size() && i < cap; ++i) out[i] = c[i];
+    *count = (int)c.size();
+    return SV_OK;
+}
+
+sv_status sv_features(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const sv_schedule *s, float *out)
+{
+    if (n < 1 || n > 36) return fail(SV_ERR_INVALID_ARG, "n must be in [1, 36]");
+    if (dtype != SV_COMPLEX64 && dtype != SV_COMPLEX128) return fail(SV_ERR_INVALID_ARG, "unknown dtype");
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    if (sv_status st = check_schedule(s, dtype)) return st;
+    const svp::PlanConfig c = config_for(n, dtype, s);
+    std::vector<int> l2p(n);
+    for (int q = 0; q < n; ++q) l2p[q] = q;
+    svp::Plan plan;
+    std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, l2p, plan);
+    if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+    plan_features(n, dtype, c, plan, out);
+    return SV_OK;
+}
+
+sv_status sv_jit_precompile(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const sv_schedule *s)
+{
+    if (n < 1 || n > 36) return fail(SV_ERR_INVALID_ARG, "n must be in [1, 36]");
+    if (dtype != SV_COMPLEX64 && dtype != SV_COMPLEX128) return fail(SV_ERR_INVALID_ARG, "unknown dtype");
+    if (sv_status st = check_schedule(s, dtype)) return st;
+    const svp::PlanConfig c = config_for(n, dtype, s);
+    std::vector<int> l2p(n);
+    for (int q = 0; q < n; ++q) l2p[q] = q;
+    svp::Plan plan;
+    std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, l2p, plan);
+    if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+    if (svj::precompile(plan, dtype, &err) != hipSuccess)
+        return fail(SV_ERR_DEVICE, err.empty() ? std::string("pass compilation failed") : err);
+    return SV_OK;
+}
+
+sv_status sv_tune_time(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *cands, int ncand,
+                       int repeats, double *ms_out, double *compile_ms)
+{
+    if (sv_status st = check_handle(h)) return st;
+    if (!cands || ncand < 1) return fail(SV_ERR_INVALID_ARG, "no candidates");
+    if (!ms_out) return fail(SV_ERR_INVALID_ARG, "ms_out is null");
+    if (repeats < 1 || repeats > 100) return fail(SV_ERR_INVALID_ARG, "repeats must be in [1, 100]");
+    std::vector<sv_schedule> cs(cands, cands + ncand);
+    for (sv_schedule &c : cs) {
+        if (sv_status st = check_schedule(&c, h->dtype)) return st;
+        c.tuner = SV_TUNER_NONE;
+    }
+    {
+        svp::Plan probe;
+        std::string err = svp::make_plan(config_from(h, &cs[0]), reinterpret_cast<const svp::RawGate *>(gates), m,
+                                         h->l2p, probe);
+        if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+    }
+    if (svj::cache_size() > 256) {
+        if (hipError_t e = svj::trim_cache(128); e != hipSuccess) return hip_fail(e, "kernel cache trim");
+    }
+    const size_t nb = amp_bytes(h->dtype) << h->n;
+    void *scratch = nullptr;
+    if (dev_alloc(&scratch, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SV_ERR_OUT_OF_MEMORY, "tuner scratch state does not fit");
+    }
+    sv_handle tmp = nullptr;
+    sv_status rc = status_of(hipMemcpyAsync(scratch, h->buf, nb, hipMemcpyDeviceToDevice, h->stream), "copy");
+    if (rc == SV_OK) rc = sv_wrap(h->n, (sv_dtype)h->dtype, scratch, nb, h->stream, &tmp);
+    for (int i = 0; i < ncand && rc == SV_OK; ++i) {
+        const svp::PlanConfig c = config_from(h, &cs[i]);
+        svp::Plan plan;
+        std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, h->l2p, plan);
+        if (!err.empty()) {
+            rc = fail(SV_ERR_INVALID_ARG, err);
+            break;
+        }
+        double cms = 0.0;
+        const char *jenv = std::getenv("SV_JIT");
+        if (!(jenv && jenv[0] == '0')) {
+            std::vector<const void *> handles;
+            if (svj::prepare_plan(plan, h->dtype, handles, &err, &cms) != hipSuccess) {
+                rc = fail(SV_ERR_DEVICE, err.empty() ? std::string("pass compilation failed") : err);
+                break;
+            }
+        }
+        if (compile_ms) compile_ms[i] = cms;
+        std::vector<double> t;
+        for (int rep = 0; rep <= repeats && rc == SV_OK; ++rep) {
+            // every run starts from the caller's layout so all runs share one
+            // plan; the scratch contents are not needed afterwards
+            tmp->l2p = h->l2p;
+            rc = sv_apply_circuit(tmp, gates, m, &cs[i]);
+            sv_stats st{};
+            if (rc == SV_OK) rc = sv_stats_get(tmp, &st);
+            if (rc == SV_OK && rep > 0) t.push_back(st.device_ms);
+        }
+        if (rc != SV_OK) break;
+        std::sort(t.begin(), t.end());
+        ms_out[i] = t[t.size() / 2];
+    }
+    if (tmp) sv_destroy(tmp);
+    hipStreamSynchronize(h->stream);
+    hipFree(scratch);
+    return rc;
+}
+
 sv_status sv_tune(sv_handle h, const sv_gate *gates, size_t m, int mode, sv_schedule *out)
 {
-    if (sv_status s = check_handle(h)) return s;
-    (void)gates;
-    (void)m;
-    (void)mode;
-    (void)out;
-    return fail(SV_ERR_UNSUPPORTED, "tuner not available in this build");
+    if (sv_status st = check_handle(h)) return st;
+    if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
+    if (mode != SV_TUNER_EXHAUSTIVE && mode != SV_TUNER_LEARNED) return fail(SV_ERR_INVALID_ARG, "unknown tuner mode");
+    const std::vector<sv_schedule> cs = candidates(h->n, h->dtype);
+    CostModel model;
+    if (mode == SV_TUNER_LEARNED) {
+        std::lock_guard<std::mutex> lk(g_model_mu);
+        model = g_model;
+    }
+    if (mode == SV_TUNER_LEARNED && !model.params.empty()) {
+        const int in = model.in, nc = (int)cs.size();
+        const svk::MlpLayout L = svk::mlp_layout(in);
+        // host layout of the device buffer: params | norm | X | y | argmin
+        std::vector<float> host((size_t)L.count + 2 * in + (size_t)nc * in + nc + 1, 0.f);
+        std::copy(model.params.begin(), model.params.end(), host.begin());
+        std::copy(model.norm.begin(), model.norm.end(), host.begin() + L.count);
+        float *X = host.data() + L.count + 2 * in;
+        for (int i = 0; i < nc; ++i) {
+            const svp::PlanConfig c = config_from(h, &cs[i]);
+            svp::Plan plan;
+            std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, h->l2p, plan);
+            if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+            plan_features(h->n, h->dtype, c, plan, X + (size_t)i * in);
+        }
+        float *d = nullptr;
+        if (dev_alloc((void **)&d, host.size() * sizeof(float)) != hipSuccess)
+            return fail(SV_ERR_OUT_OF_MEMORY, "cost model buffer");
+        int best = -1;
+        sv_status rc = status_of(hipMemcpyAsync(d, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice,
+                                                h->stream), "upload");
+        float *dy = d + L.count + 2 * in + (size_t)nc * in;
+        if (rc == SV_OK)
+            rc = status_of(svk::mlp_forward(d, in, d + L.count, d + L.count + 2 * in, nc, dy, (int *)(dy + nc),
+                                            h->stream), "cost model");
+        if (rc == SV_OK)
+            rc = status_of(hipMemcpyAsync(&best, dy + nc, sizeof(int), hipMemcpyDeviceToHost, h->stream), "readback");
+        if (rc == SV_OK) rc = status_of(hipStreamSynchronize(h->stream), "sync");
+        hipFree(d);
+        if (rc != SV_OK) return rc;
+        if (best < 0 || best >= nc) return fail(SV_ERR_DEVICE, "cost model returned no candidate");
+        *out = cs[best];
+        return SV_OK;
+    }
+    std::vector<double> ms(cs.size(), 0.0);
+    if (sv_status st = sv_tune_time(h, gates, m, cs.data(), (int)cs.size(), 3, ms.data(), nullptr)) return st;
+    size_t best = 0;
+    for (size_t i = 1; i < ms.size(); ++i)
+        if (ms[i] < ms[best]) best = i;
+    *out = cs[best];
+    return SV_OK;
+}
+
+sv_status sv_set_cost_model(const float *params, int in, const float *norm)
+{
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    if (!params) {
+        g_model = CostModel{};
+        return SV_OK;
+    }
+    if (in != SV_FEATURES) return fail(SV_ERR_INVALID_ARG, "the cost model reads SV_FEATURES inputs");
+    const svk::MlpLayout L = svk::mlp_layout(in);
+    CostModel m;
+    m.in = in;
+    m.params.assign(params, params + L.count);
+    for (float v : m.params)
+        if (!std::isfinite(v)) return fail(SV_ERR_INVALID_ARG, "non-finite parameter");
+    m.norm.resize(2 * (size_t)in);
+    for (int i = 0; i < in; ++i) {
+        m.norm[i] = norm ? norm[i] : 0.f;
+        m.norm[in + i] = norm ? norm[in + i] : 1.f;
+    }
+    g_model = std::move(m);
+    return SV_OK;
+}
+
+size_t sv_mlp_param_count(int in)
+{
+    if (in < 1 || in > svk::kMlpMaxIn) return 0;
+    return (size_t)svk::mlp_layout(in).count;
+}
+
+size_t sv_mlp_workspace_bytes(int in, int batch)
+{
+    if (in < 1 || in > svk::kMlpMaxIn || batch < 1) return 0;
+    return sizeof(float) * (size_t)svk::mlp_grad_groups(batch) * (size_t)(svk::mlp_layout(in).count + 1);
+}
+
+sv_status sv_mlp_forward(const float *params, int in, const float *norm, const float *x, int batch, float *y,
+                         void *stream)
+{
+    if (in < 1 || in > svk::kMlpMaxIn) return fail(SV_ERR_INVALID_ARG, "in must be in [1, 32]");
+    if (batch < 1) return fail(SV_ERR_INVALID_ARG, "batch < 1");
+    if (!params || !x || !y) return fail(SV_ERR_INVALID_ARG, "null pointer");
+    return status_of(svk::mlp_forward(params, in, norm, x, batch, y, nullptr, (hipStream_t)stream), "mlp forward");
+}
+
+sv_status sv_mlp_grad(const float *params, int in, const float *norm, const float *x, const float *target,
+                      int batch, float *grad, float *loss, void *workspace, void *stream)
+{
+    if (in < 1 || in > svk::kMlpMaxIn) return fail(SV_ERR_INVALID_ARG, "in must be in [1, 32]");
+    if (batch < 1) return fail(SV_ERR_INVALID_ARG, "batch < 1");
+    if (!params || !x || !target || !grad || !workspace) return fail(SV_ERR_INVALID_ARG, "null pointer");
+    return status_of(svk::mlp_grad(params, in, norm, x, target, batch, grad, loss, (float *)workspace,
+                                   (hipStream_t)stream),
+                     "mlp grad");
+}
+
+sv_status sv_mlp_adam(float *params, float *m, float *v, const float *grad, size_t count, float lr, float beta1,
+                      float beta2, float eps, int step, void *stream)
+{
+    if (!params || !m || !v || !grad) return fail(SV_ERR_INVALID_ARG, "null pointer");
+    if (count < 1 || count > (size_t)svk::kMlpMaxParams) return fail(SV_ERR_INVALID_ARG, "count out of range");
+    if (step < 1) return fail(SV_ERR_INVALID_ARG, "step counts from 1");
+    if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(SV_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+    return status_of(svk::mlp_adam(params, m, v, grad, (int)count, lr, beta1, beta2, eps, step, (hipStream_t)stream),
+                     "mlp adam");
 }
 
 }  // extern "C"
@@ -813,8 +1139,8 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     for (int i = 0; i < count; ++i) min_n = std::min(min_n, hs[i]->n);
     int l = base.l > 0 ? base.l : svp::default_block_qubits(dtype);
     l = std::min(l, min_n);
-    const int logr = std::min(4, l);
-    if (base.mode != 1 || base.remap != 0 || logr < 3) {
+    const int logr = std::min(s && s->reg_qubits > 0 ? s->reg_qubits : 4, l);
+    if (base.mode != 1 || base.remap != 0 || logr < 3 || logr > 4) {
         *sequential = true;
         return nullptr;
     }
@@ -1049,6 +1375,8 @@ sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, 
     if (sv_status st = check_batch(hs, count, gates, m)) return st;
     if (count == 0) return SV_OK;
     if (sv_status st = check_schedule(s, hs[0]->dtype)) return st;
+    if (s && s->tuner != SV_TUNER_NONE)
+        return fail(SV_ERR_UNSUPPORTED, "batches are tuned with sv_tune_batch, not through the schedule");
     bool sequential = false;
     std::string err;
     BatchEntry *e = get_batch(hs, count, gates, m, s, &sequential, &err);

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -32,10 +34,12 @@ struct Kernel {
 struct Entry {
     hipModule_t mod = nullptr;
     std::vector<Kernel> kernels;
+    uint64_t last_use = 0;
 };
 
 std::mutex g_mu;
 std::unordered_map<std::string, Entry> g_cache;
+uint64_t g_clock = 0;
 int g_cus = 0;
 
 std::string hexd(double x)
@@ -201,8 +205,10 @@ std::string compile_check(const std::string &src)
     return out;
 }
 
-hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void *> &handles, std::string *err)
+hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void *> &handles, std::string *err,
+                        double *compile_ms)
 {
+    if (compile_ms) *compile_ms = 0.0;
     handles.assign(plan.steps.size(), nullptr);
     bool any = false;
     for (const svp::Step &s : plan.steps) any = any || s.kind == svp::ST_K2;
@@ -218,7 +224,10 @@ hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void
     auto it = g_cache.find(src);
     if (it == g_cache.end()) {
         std::vector<char> code;
+        const auto t0 = std::chrono::steady_clock::now();
         hipError_t he = compile(src, code, err);
+        if (compile_ms)
+            *compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (he != hipSuccess) return he;
         Entry e;
         he = hipModuleLoadData(&e.mod, code.data());
@@ -238,6 +247,7 @@ hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void
         }
         it = g_cache.emplace(src, std::move(e)).first;
     }
+    it->second.last_use = ++g_clock;
     size_t k = 0;
     for (size_t i = 0; i < plan.steps.size(); ++i)
         if (plan.steps[i].kind == svp::ST_K2) handles[i] = &it->second.kernels[k++];
@@ -253,6 +263,37 @@ hipError_t launch(const void *handle, void *S, const svp::K2Args &a, hipStream_t
     svp::K2Args args = a;
     void *params[] = {&S, &args};
     return hipModuleLaunchKernel(e.fn, (unsigned)grid, 1, 1, e.threads, 1, 1, 0, st, params, nullptr);
+}
+
+hipError_t precompile(const svp::Plan &plan, int dtype, std::string *err)
+{
+    bool any = false;
+    for (const svp::Step &s : plan.steps) any = any || s.kind == svp::ST_K2;
+    if (!any) return hipSuccess;
+    std::vector<char> code;
+    return compile(generate_plan(plan, dtype), code, err);
+}
+
+hipError_t trim_cache(size_t keep)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_cache.size() <= keep) return hipSuccess;
+    // kernels of an evicted module may still be queued on some stream
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    std::vector<std::pair<uint64_t, const std::string *>> order;
+    for (auto &kv : g_cache) order.emplace_back(kv.second.last_use, &kv.first);
+    std::sort(order.begin(), order.end());
+    const size_t drop = g_cache.size() - keep;
+    std::vector<std::string> victims;
+    for (size_t i = 0; i < drop; ++i) victims.push_back(*order[i].second);
+    for (const std::string &v : victims) {
+        auto it = g_cache.find(v);
+        if (it->second.mod) e = hipModuleUnload(it->second.mod);
+        g_cache.erase(it);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 size_t cache_size()

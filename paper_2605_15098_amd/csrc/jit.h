@@ -17,7 +17,17 @@ std::string generate(const svp::Step &s, const svp::Plan &plan, int dtype);
 // plan, as one module; handles[i] identifies step i's kernel for launch()
 // (nullptr for steps that are not block passes). On a compile error, *err
 // holds the compiler log.
-hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void *> &handles, std::string *err);
+// compile_ms (optional) receives the compile time, 0 on a cache hit.
+hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void *> &handles, std::string *err,
+                        double *compile_ms = nullptr);
+
+// Compile the plan's passes without loading them (no device needed); the
+// compiler's own on-disk cache keeps the result for later prepare_plan calls.
+hipError_t precompile(const svp::Plan &plan, int dtype, std::string *err);
+
+// Unload all but the `keep` most recently used modules (synchronizes the
+// device first).
+hipError_t trim_cache(size_t keep);
 
 // Source of all block passes of a plan (what prepare_plan compiles).
 std::string generate_plan(const svp::Plan &plan, int dtype);

@@ -46,7 +46,8 @@ class sv_schedule(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("block_qubits", ctypes.c_int32),
                 ("outer_qubits", ctypes.c_int32), ("fuse_k", ctypes.c_int32),
                 ("swap_policy", ctypes.c_int32), ("remap", ctypes.c_int32),
-                ("diag_free", ctypes.c_int32), ("tuner", ctypes.c_int32)]
+                ("diag_free", ctypes.c_int32), ("tuner", ctypes.c_int32),
+                ("reg_qubits", ctypes.c_int32)]
 
 
 class sv_stats(ctypes.Structure):
@@ -60,7 +61,7 @@ class sv_stats(ctypes.Structure):
 
 
 def schedule(mode="partitioned", block_qubits=0, outer_qubits=0, fuse_k=1, swap_policy="lookahead",
-             remap="virtual", diag_free=True, tuner="none") -> sv_schedule:
+             remap="virtual", diag_free=True, tuner="none", reg_qubits=0) -> sv_schedule:
     s = sv_schedule()
     s.mode = {"plain": SV_PLAIN, "partitioned": SV_PARTITIONED}.get(mode, mode)
     s.block_qubits = int(block_qubits)
@@ -71,7 +72,12 @@ def schedule(mode="partitioned", block_qubits=0, outer_qubits=0, fuse_k=1, swap_
     s.diag_free = int(bool(diag_free))
     s.tuner = {"none": SV_TUNER_NONE, "exhaustive": SV_TUNER_EXHAUSTIVE,
                "learned": SV_TUNER_LEARNED}.get(tuner, tuner)
+    s.reg_qubits = int(reg_qubits)
     return s
+
+
+def schedule_dict(s: sv_schedule) -> dict:
+    return {name: int(getattr(s, name)) for name, _ in sv_schedule._fields_}
 
 
 def paper_schedule(block_qubits: int) -> sv_schedule:
@@ -111,6 +117,21 @@ _SIGS = {
                  ctypes.POINTER(sv_stats)], ctypes.c_int32),
     "sv_tune": ([_VP, _VP, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(sv_schedule)],
                 ctypes.c_int32),
+    "sv_tune_candidates": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(sv_schedule), ctypes.c_int,
+                            ctypes.POINTER(ctypes.c_int)], ctypes.c_int32),
+    "sv_tune_time": ([_VP, _VP, ctypes.c_size_t, ctypes.POINTER(sv_schedule), ctypes.c_int, ctypes.c_int,
+                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int32),
+    "sv_jit_precompile": ([ctypes.c_int, ctypes.c_int, _VP, ctypes.c_size_t, ctypes.POINTER(sv_schedule)],
+                          ctypes.c_int32),
+    "sv_features": ([ctypes.c_int, ctypes.c_int, _VP, ctypes.c_size_t, ctypes.POINTER(sv_schedule),
+                     ctypes.POINTER(ctypes.c_float)], ctypes.c_int32),
+    "sv_mlp_param_count": ([ctypes.c_int], ctypes.c_size_t),
+    "sv_mlp_workspace_bytes": ([ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+    "sv_mlp_forward": ([_VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP, _VP], ctypes.c_int32),
+    "sv_mlp_grad": ([_VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP, _VP], ctypes.c_int32),
+    "sv_mlp_adam": ([_VP, _VP, _VP, _VP, ctypes.c_size_t, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                     ctypes.c_float, ctypes.c_int, _VP], ctypes.c_int32),
+    "sv_set_cost_model": ([_VP, ctypes.c_int, _VP], ctypes.c_int32),
     "sv_layout": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int32),
     "sv_set_kernel_timing": ([_VP, ctypes.c_int], ctypes.c_int32),
     "sv_debug_inject_fault": ([ctypes.c_int], ctypes.c_int32),
@@ -139,7 +160,7 @@ def header_functions(path: str = HEADER):
     """Names of the functions include/sv.h declares."""
     with open(path) as fh:
         text = fh.read()
-    return sorted(set(re.findall(r"^(?:sv_status|const char \*)\s*(sv_\w+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:sv_status|const char \*|size_t)\s*(sv_\w+)\(", text, re.M)))
 
 
 def _check(status: int):
@@ -311,6 +332,98 @@ def sv_tune(h, gates, mode=SV_TUNER_EXHAUSTIVE) -> sv_schedule:
     _check(load().sv_tune(_VP(h), g.ctypes.data if len(g) else None, len(g), int(mode),
                           ctypes.byref(out)))
     return out
+
+
+SV_FEATURES = 16
+FEATURE_NAMES = ["n", "bytes_per_amp", "block_qubits", "reg_qubits", "lookahead", "fuse_k", "gates",
+                 "block_passes", "swap_passes", "plain_sweeps", "log2_bytes", "ops", "max_pass_ops",
+                 "dense_ops", "diag_ops", "layout_ops"]
+
+
+def sv_tune_candidates(n: int, dtype="c64") -> list:
+    cnt = ctypes.c_int(0)
+    _check(load().sv_tune_candidates(int(n), DTYPES[dtype], None, 0, ctypes.byref(cnt)))
+    arr = (sv_schedule * cnt.value)()
+    _check(load().sv_tune_candidates(int(n), DTYPES[dtype], arr, cnt.value, ctypes.byref(cnt)))
+    return list(arr)
+
+
+def sv_tune_time(h, gates, cands: Sequence[sv_schedule], repeats: int = 3):
+    """(ms per candidate, compile ms per candidate) measured on a scratch copy."""
+    g = _gates(gates)
+    arr = (sv_schedule * len(cands))(*cands)
+    ms = (ctypes.c_double * len(cands))()
+    cms = (ctypes.c_double * len(cands))()
+    _check(load().sv_tune_time(_VP(h), g.ctypes.data if len(g) else None, len(g), arr, len(cands),
+                               int(repeats), ms, cms))
+    return list(ms), list(cms)
+
+
+def sv_jit_precompile(n: int, dtype, gates, sched: sv_schedule) -> None:
+    g = _gates(gates)
+    _check(load().sv_jit_precompile(int(n), DTYPES[dtype], g.ctypes.data if len(g) else None, len(g),
+                                    ctypes.byref(sched)))
+
+
+def sv_features(n: int, dtype, gates, sched: sv_schedule) -> np.ndarray:
+    g = _gates(gates)
+    out = np.zeros(SV_FEATURES, dtype=np.float32)
+    _check(load().sv_features(int(n), DTYPES[dtype], g.ctypes.data if len(g) else None, len(g),
+                              ctypes.byref(sched), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def sv_mlp_param_count(in_dim: int) -> int:
+    return int(load().sv_mlp_param_count(int(in_dim)))
+
+
+def sv_mlp_workspace_bytes(in_dim: int, batch: int) -> int:
+    return int(load().sv_mlp_workspace_bytes(int(in_dim), int(batch)))
+
+
+def _dptr(t) -> Optional[int]:
+    """Device address of a CUDA tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch.float32":
+        raise TypeError("expected a contiguous float32 device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+def sv_mlp_forward(params, in_dim: int, norm, x, batch: int, y, stream=None) -> None:
+    _check(load().sv_mlp_forward(_dptr(params), int(in_dim), _dptr(norm), _dptr(x), int(batch), _dptr(y),
+                                 _stream(stream)))
+
+
+def sv_mlp_grad(params, in_dim: int, norm, x, target, batch: int, grad, loss, workspace, stream=None) -> None:
+    _check(load().sv_mlp_grad(_dptr(params), int(in_dim), _dptr(norm), _dptr(x), _dptr(target), int(batch),
+                              _dptr(grad), _dptr(loss), _dptr(workspace), _stream(stream)))
+
+
+def sv_mlp_adam(params, m, v, grad, count: int, lr: float, beta1: float, beta2: float, eps: float, step: int,
+                stream=None) -> None:
+    _check(load().sv_mlp_adam(_dptr(params), _dptr(m), _dptr(v), _dptr(grad), int(count), float(lr),
+                              float(beta1), float(beta2), float(eps), int(step), _stream(stream)))
+
+
+def sv_set_cost_model(params: Optional[np.ndarray], in_dim: int = SV_FEATURES,
+                      norm: Optional[np.ndarray] = None) -> None:
+    """Install (host float32 arrays) or, with params None, remove the cost model."""
+    if params is None:
+        _check(load().sv_set_cost_model(None, int(in_dim), None))
+        return
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    nrm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+    if p.size != sv_mlp_param_count(in_dim):
+        raise ValueError("parameter count does not match the network")
+    _check(load().sv_set_cost_model(p.ctypes.data, int(in_dim), None if nrm is None else nrm.ctypes.data))
 
 
 def sv_set_kernel_timing(h, on: bool = True) -> None:

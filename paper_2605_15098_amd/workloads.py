@@ -239,3 +239,16 @@ def circuit_random_train(c: int, depth: int = 200, lo: int = 20, hi: int = 26):
     rng = np.random.default_rng([1005, c])
     n = int(rng.integers(lo, hi + 1))
     return n, random_circuit(n, depth, rng)
+
+
+def mlp_init_params(in_dim: int, seed: int, hidden: int = 64) -> np.ndarray:
+    """Seeded initial parameters of the cost-model network, flat float64 in
+    the order W1 (hidden x in), b1, W2 (hidden x hidden), b2, w3, b3:
+    He-uniform weights (bound sqrt(6 / fan_in)) and zero biases."""
+    rng = np.random.default_rng(seed)
+    a1 = math.sqrt(6.0 / in_dim)
+    a2 = math.sqrt(6.0 / hidden)
+    return np.concatenate([
+        rng.uniform(-a1, a1, size=hidden * in_dim), np.zeros(hidden),
+        rng.uniform(-a2, a2, size=hidden * hidden), np.zeros(hidden),
+        rng.uniform(-a2, a2, size=hidden), np.zeros(1)])

@@ -155,3 +155,53 @@ def test_empty_and_swap_only_circuits():
     for s in (sv.schedule("plain"), sv.schedule(), sv.paper_schedule(3)):
         st = sv.sv_plan(5, "c64", g, s)
         assert st["passes"] == 0
+
+
+def test_tuner_candidates():
+    c = sv.sv_tune_candidates(30, "c64")
+    assert len(c) == 12
+    got = {(x.block_qubits, x.reg_qubits, x.swap_policy) for x in c}
+    assert got == {(l, r, p) for l in (11, 12, 13) for r in (4, 5) for p in (0, 1)}
+    assert all(x.mode == sv.SV_PARTITIONED and x.fuse_k == 1 and x.tuner == 0 for x in c)
+    c = sv.sv_tune_candidates(30, "c128")
+    assert {(x.block_qubits, x.reg_qubits) for x in c} == {(l, r) for l in (10, 11, 12) for r in (3, 4)}
+    small = sv.sv_tune_candidates(3, "c64")
+    assert all(x.reg_qubits <= x.block_qubits <= 3 for x in small) and len(small) == 6
+    with pytest.raises(sv.SvError):
+        sv.sv_tune_candidates(0, "c64")
+
+
+def test_features_agree_with_the_plan():
+    for n, g in ((24, W.qpe_gates(24, 0.4)), W.circuit_random_train(5)):
+        for c in sv.sv_tune_candidates(n, "c64"):
+            f = sv.sv_features(n, "c64", g, c)
+            st = sv.sv_plan(n, "c64", g, c)
+            assert f[0] == n and f[1] == 8 and f[2] == c.block_qubits
+            assert f[3] == c.reg_qubits and f[4] == (c.swap_policy == sv.SV_SWAP_LOOKAHEAD)
+            assert f[6] == st["gates"] and f[7] == st["passes"]
+            assert f[10] == pytest.approx(np.log2(st["bytes"]), abs=1e-4)
+            assert f[13] + f[14] + f[15] <= f[11] and f[12] <= f[11]
+    # plain schedule: every gate is a sweep
+    g = W.qpe_gates(12, 0.4)
+    f = sv.sv_features(12, "c128", g, sv.schedule("plain"))
+    assert f[1] == 16 and f[2] == 0 and f[7] == 0 and f[9] == W.qpe_gate_count(12)[0]
+
+
+def test_schedule_field_validation():
+    g = W.qpe_gates(8, 0.1)
+    for bad, status in ((dict(reg_qubits=-1), sv.SV_ERR_INVALID_ARG), (dict(reg_qubits=6), sv.SV_ERR_UNSUPPORTED),
+                        (dict(tuner=7), sv.SV_ERR_INVALID_ARG)):
+        with pytest.raises(sv.SvError) as e:
+            sv.sv_plan(8, "c64", g, sv.schedule(**bad))
+        assert e.value.status == status
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(8, "c128", g, sv.schedule(reg_qubits=5))
+    assert e.value.status == sv.SV_ERR_UNSUPPORTED
+    assert sv.sv_plan(8, "c64", g, sv.schedule(reg_qubits=5))["passes"] >= 1
+
+
+def test_precompile_without_device():
+    g = W.qpe_gates(12, 0.3)
+    sv.sv_jit_precompile(12, "c64", g, sv.schedule(block_qubits=10))
+    with pytest.raises(sv.SvError):
+        sv.sv_jit_precompile(12, "c64", W.gates_from_tuples([("H", 12, -1, 0.0)]), sv.schedule())

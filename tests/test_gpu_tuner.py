@@ -1,0 +1,142 @@
+"""GPU tests of schedule tuning: exhaustive and learned selection, the
+register-tile schedule field, and tuning inside sv_apply_circuit.
+
+A schedule only changes the order and layout of the work, so the state after
+a tuned run must match the oracle (complex64 <= 2e-5, complex128 <= 1e-12)
+and the state before tuning must be left untouched, bit for bit.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from oracle import qpe as cf
+from paper_2605_15098_amd import sv
+from paper_2605_15098_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = {"c128": 1e-12, "c64": 2e-5}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def fields(s):
+    return tuple(int(getattr(s, f)) for f, _ in sv.sv_schedule._fields_)
+
+
+def passes_model():
+    """A network whose prediction is the block-pass count (feature 7): one
+    live unit per layer, identity standardisation."""
+    t = {name: np.zeros(shape) if shape else 0.0 for name, (_, shape) in mlp.layout(16).items()}
+    t["W1"][0, 7] = 1.0
+    t["W2"][0, 0] = 1.0
+    t["w3"][0] = 1.0
+    return mlp.pack(t, 16).astype(np.float32)
+
+
+@pytest.mark.parametrize("dtype,reg", [("c64", 3), ("c64", 5), ("c128", 3)])
+def test_register_tile_schedules_match_oracle(dtype, reg):
+    rng = np.random.default_rng(60 + reg)
+    n = 14
+    g = W.random_mixed_circuit(n, 120, rng)
+    want = oracle.apply(n, g)
+    for l in (9, 12):
+        log(f"case reg_qubits={reg} l={l} dtype={dtype}")
+        s = sv.StateVector(n, dtype)
+        s.apply(g, sv.schedule(block_qubits=l, reg_qubits=reg))
+        got = s.state()
+        s.close()
+        assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
+def test_exhaustive_tune_leaves_state_and_picks_a_candidate(monkeypatch):
+    monkeypatch.setenv("SV_JIT", "0")  # op interpreter: no compile per candidate
+    n = 16
+    g = W.qpe_gates(n, 0.3)
+    s = sv.StateVector(n, "c64")
+    s.apply(W.random_mixed_circuit(n, 30, np.random.default_rng(1)), sv.schedule(block_qubits=10))
+    before, lay = s.state(), s.layout()
+    log("case exhaustive tune")
+    best = sv.sv_tune(s.h, g, sv.SV_TUNER_EXHAUSTIVE)
+    assert np.array_equal(s.state().view(np.uint8), before.view(np.uint8))
+    assert s.layout() == lay
+    assert fields(best) in [fields(c) for c in sv.sv_tune_candidates(n, "c64")]
+    cands = sv.sv_tune_candidates(n, "c64")[:3]
+    ms, cms = sv.sv_tune_time(s.h, g, cands, repeats=2)
+    assert all(np.isfinite(ms)) and min(ms) > 0 and min(cms) >= 0
+    s.close()
+
+
+def test_learned_tune_takes_the_model_argmin_and_runs_correctly():
+    n = 18
+    g = W.qpe_gates(n, 0.71)
+    cands = sv.sv_tune_candidates(n, "c64")
+    feats = np.stack([sv.sv_features(n, "c64", g, c) for c in cands])
+    sv.sv_set_cost_model(passes_model())
+    try:
+        s = sv.StateVector(n, "c64")
+        log("case learned tune")
+        pick = sv.sv_tune(s.h, g, sv.SV_TUNER_LEARNED)
+        assert fields(pick) == fields(cands[int(np.argmin(feats[:, 7]))])
+        s.apply(g, pick)
+        got = s.state()
+        s.close()
+        assert np.max(np.abs(got - cf.qpe_state(n, 0.71))) <= TOL["c64"]
+        # tuning requested through the schedule itself
+        s = sv.StateVector(n, "c64")
+        s.apply(g, sv.schedule(tuner="learned"))
+        assert np.max(np.abs(s.state() - cf.qpe_state(n, 0.71))) <= TOL["c64"]
+        s.close()
+    finally:
+        sv.sv_set_cost_model(None)
+
+
+def test_learned_and_exhaustive_schedules_agree_on_the_state(monkeypatch):
+    monkeypatch.setenv("SV_JIT", "0")
+    rng = np.random.default_rng(70)
+    n = 15
+    g = W.random_circuit(n, 200, rng)
+    want = oracle.apply(n, g)
+    outs = []
+    sv.sv_set_cost_model(passes_model())
+    try:
+        for mode in ("learned", "exhaustive"):
+            log(f"case tuned apply {mode}")
+            s = sv.StateVector(n, "c128")
+            s.apply(g, sv.schedule(tuner=mode))
+            outs.append(s.state())
+            s.close()
+    finally:
+        sv.sv_set_cost_model(None)
+    for o in outs:
+        assert np.max(np.abs(o - want)) <= TOL["c128"]
+
+
+def test_learned_without_model_falls_back_to_exhaustive(monkeypatch):
+    monkeypatch.setenv("SV_JIT", "0")
+    sv.sv_set_cost_model(None)
+    s = sv.StateVector(12, "c64")
+    pick = sv.sv_tune(s.h, W.qpe_gates(12, 0.2), sv.SV_TUNER_LEARNED)
+    assert fields(pick) in [fields(c) for c in sv.sv_tune_candidates(12, "c64")]
+    s.close()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(sv.__file__), "cost_model_c64.npz")),
+                    reason="no trained cost model in the package")
+def test_trained_model_picks_a_candidate():
+    from paper_2605_15098_amd import costmodel
+    costmodel.install()
+    try:
+        n, g = W.circuit_random_train(3)
+        s = sv.StateVector(n, "c64")
+        pick = sv.sv_tune(s.h, g, sv.SV_TUNER_LEARNED)
+        assert fields(pick) in [fields(c) for c in sv.sv_tune_candidates(n, "c64")]
+        s.close()
+    finally:
+        sv.sv_set_cost_model(None)
