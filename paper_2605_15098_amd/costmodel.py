@@ -14,8 +14,9 @@ the library's kernels (sv_mlp_*); this module only moves arrays.
 
 Every pass kernel a candidate needs is compiled at run time (several seconds
 per schedule), so `collect` and `eval` first compile all candidates in a pool
-of worker processes that never touch the GPU; the compiler's on-disk cache
-then serves the timed process.
+of worker processes that never touch the GPU; the library's on-disk module
+cache (SV_JIT_CACHE_DIR, default under the temp directory) then serves the
+timed process.
 """
 from __future__ import annotations
 
@@ -74,10 +75,18 @@ def _precompile_job(job):
     return time.perf_counter() - t0
 
 
+def use_jit_cache() -> str:
+    import tempfile
+    d = os.environ.setdefault("SV_JIT_CACHE_DIR", os.path.join(tempfile.gettempdir(), "svmi_jit_cache"))
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
 def precompile(jobs: Sequence[tuple], workers: int) -> List[float]:
     """Compile every (n, dtype, circuit kind, index, schedule fields) job in a
     pool of processes that only run the compiler. Must run before this
     process first touches the GPU. Returns the compile seconds per job."""
+    use_jit_cache()
     if workers <= 1 or len(jobs) <= 1:
         return [_precompile_job(j) for j in jobs]
     ctx = mp.get_context("spawn")
@@ -126,8 +135,8 @@ def collect(idxs: Sequence[int], dtype: str = "c64", repeats: int = 3, workers: 
         cid += [i] * len(cands)
         cidx += list(range(len(cands)))
         cms_all += cms
-        if (k + 1) % 10 == 0 or k + 1 == len(idxs):
-            log(f"timed {k + 1}/{len(idxs)} circuits (n={n}: best {min(ms):.3f} ms, worst {max(ms):.3f} ms)")
+        log(f"timed {k + 1}/{len(idxs)}: circuit {i} n={n} best {min(ms):.3f} ms, worst {max(ms):.3f} ms, "
+            f"load/compile {sum(cms) / 1e3:.1f} s")
     return {"X": np.concatenate(rows).astype(np.float32), "ms": np.asarray(ys),
             "circuit": np.asarray(cid), "cand": np.asarray(cidx),
             "compile_s_pool": np.asarray(csec), "compile_ms_timed_process": np.asarray(cms_all)}

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
+#include <unistd.h>
 #include <cstring>
 #include <mutex>
 #include <sstream>
@@ -155,7 +157,7 @@ std::string generate_plan(const svp::Plan &plan, int dtype)
     return src;
 }
 
-static hipError_t compile(const std::string &src, std::vector<char> &code, std::string *err)
+static hipError_t compile_rtc(const std::string &src, std::vector<char> &code, std::string *err)
 {
     hiprtcProgram prog;
     const char *headers[] = {kJitAbiH, kJitDeviceH};
@@ -182,6 +184,59 @@ static hipError_t compile(const std::string &src, std::vector<char> &code, std::
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
     return hipSuccess;
+}
+
+// Optional on-disk cache of compiled passes, shared by processes: with
+// SV_JIT_CACHE_DIR set, a pass module is stored as <dir>/svk2-<key>.co where
+// the key is two independent 64-bit FNV-1a hashes of the source text (which
+// embeds every constant) and the compiler version; a file is written under a
+// temporary name and renamed into place, so readers never see a partial one.
+static uint64_t fnv1a(const std::string &s, uint64_t h)
+{
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+static std::string cache_path(const std::string &src)
+{
+    const char *dir = std::getenv("SV_JIT_CACHE_DIR");
+    if (!dir || !*dir) return "";
+    int major = 0, minor = 0;
+    hiprtcVersion(&major, &minor);
+    const std::string tag = src + "|hiprtc " + std::to_string(major) + "." + std::to_string(minor);
+    char name[64];
+    std::snprintf(name, sizeof name, "/svk2-%016llx%016llx.co", (unsigned long long)fnv1a(tag, 0xcbf29ce484222325ull),
+                  (unsigned long long)fnv1a(tag, 0x84222325cbf29ce4ull));
+    return std::string(dir) + name;
+}
+
+static hipError_t compile(const std::string &src, std::vector<char> &code, std::string *err)
+{
+    const std::string path = cache_path(src);
+    if (!path.empty()) {
+        if (FILE *f = std::fopen(path.c_str(), "rb")) {
+            std::fseek(f, 0, SEEK_END);
+            const long size = std::ftell(f);
+            std::fseek(f, 0, SEEK_SET);
+            code.resize(size > 0 ? (size_t)size : 0);
+            const bool ok = size > 0 && std::fread(code.data(), 1, code.size(), f) == code.size();
+            std::fclose(f);
+            if (ok) return hipSuccess;
+        }
+    }
+    hipError_t e = compile_rtc(src, code, err);
+    if (e == hipSuccess && !path.empty()) {
+        const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+        if (FILE *f = std::fopen(tmp.c_str(), "wb")) {
+            const bool ok = std::fwrite(code.data(), 1, code.size(), f) == code.size();
+            std::fclose(f);
+            if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+        }
+    }
+    return e;
 }
 
 std::string compile_check(const std::string &src)

@@ -147,6 +147,12 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                                "(run python -m paper_2605_15098_amd.build)")
+        # torch's HIP runtime and ours share one HSA runtime (the first one
+        # loaded); load torch's first, the order every GPU run here uses
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             fn = getattr(lib, name)
