@@ -30,6 +30,10 @@ enum K2Kind {
     K2_DIAGRUN = 6,  // a: byte offset of a DiagRec in the table buffer
     K2_HU = 7,       // unnormalized Hadamard (a+b, a-b) on slot a, no control
     K2_SCALE = 8,    // every amplitude times v[0]
+    K2_MFMA = 9,     // dense window unitary through the matrix cores: a: byte
+                     // offset of the operand-ordered matrix in the table;
+                     // b: window qubits (4 or 5); c: packed window local bits
+                     // (5 bits each, ascending); m0: window local-bit mask
 };
 // Control of a dense op: none, a register slot, or a bit code (0..l-1 =
 // local bit tested on the thread's local index, 64 + p = memory bit p of the

@@ -209,6 +209,129 @@ __device__ __forceinline__ void k2_layout(C *a, K2Ctx &cx, const int *rb_old, co
     lds_barrier();
 }
 
+// ---- dense window through the matrix cores (16x16x4 MFMA)
+
+typedef float k2_f4 __attribute__((ext_vector_type(4)));
+typedef double k2_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct K2Mfma;
+template <> struct K2Mfma<float> {
+    using V = k2_f4;
+    static __device__ __forceinline__ V mma(float x, float y, V c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+    }
+};
+template <> struct K2Mfma<double> {
+    using V = k2_d4;
+    static __device__ __forceinline__ V mma(double x, double y, V c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+    }
+};
+
+// A KW-qubit unitary on local bits w[0] < ... < w[KW-1], applied to every
+// one of the block's 2^(l-KW) vectors through the LDS copy of the block.
+// The window's complex 2^KW matrix acts as the real matrix M' of size
+// D = 2^(KW+1) on interleaved vectors (real index 2 j + c: amplitude j of
+// the window, component c). Wave-level 16x16x4 MFMA: 16 vectors per group
+// (lane % 16), operand B[k][n] from lane 16 k + n, output D[4 q + r][n] in
+// register r of lane 16 q + n. mat holds M' in A-operand order:
+// mat[(t * D/4 + s) * 64 + lane] = M'[16 t + lane % 16][4 s + lane / 16].
+// The register layout rb is the same before and after.
+template <int LOGR, int KW, typename C>
+__device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const int *w, int l, const void *mat)
+{
+    using T = decltype(C::x);
+    using V = typename K2Mfma<T>::V;
+    constexpr int R = 1 << LOGR;
+    constexpr int D = 2 << KW;
+    constexpr int TILES = D / 16, STEPS = D / 4;
+    {
+        const uint32_t tsw = swz<C>(cx.tloc) * (uint32_t)sizeof(C);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint32_t kp = 0;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) kp |= 1u << rb[j];
+            *reinterpret_cast<C *>(cx.lds + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C)))) = a[k];
+        }
+    }
+    lds_barrier();
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    const int nwaves = (int)(blockDim.x >> 6);
+    const int col = lane & 15, q = lane >> 4;
+    uint32_t wsw[KW], wmask = 0;
+#pragma unroll
+    for (int i = 0; i < KW; ++i) {
+        wsw[i] = swz<C>(1u << w[i]);
+        wmask |= 1u << w[i];
+    }
+    const uint32_t nvec = 1u << (l - KW);
+    const int groups = (int)((nvec + 15u) >> 4);
+    const T *M = static_cast<const T *>(mat);
+    // input element of lane: amplitude j = 2 s + (q >> 1), component q & 1
+    const uint32_t in_lane = (q >> 1) ? wsw[0] : 0u;
+    // output element of lane: row 16 t + 4 q + r -> amplitude 8 t + 2 q + (r >> 1), component r & 1
+    uint32_t out_lane = 0;
+#pragma unroll
+    for (int i = 0; i < 2 && i + 1 < KW; ++i)
+        if ((q >> i) & 1) out_lane ^= wsw[i + 1];
+    for (int g = wave; g < groups; g += nwaves) {
+        const uint32_t n = (uint32_t)g * 16u + (uint32_t)col;
+        const bool valid = n < nvec;
+        uint32_t vb = 0, m = n;
+        for (int b = 0; b < l; ++b)
+            if (!((wmask >> b) & 1u)) {
+                vb |= (m & 1u) << b;
+                m >>= 1;
+            }
+        const uint32_t vsw = swz<C>(vb);
+        V acc[TILES];
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) acc[t] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            uint32_t jsw = in_lane;
+#pragma unroll
+            for (int i = 1; i < KW; ++i)
+                if (((2 * s) >> i) & 1) jsw ^= wsw[i];
+            const T *src = reinterpret_cast<const T *>(cx.lds + (vsw ^ jsw) * (uint32_t)sizeof(C));
+            const T bv = valid ? src[q & 1] : T(0);
+#pragma unroll
+            for (int t = 0; t < TILES; ++t) acc[t] = K2Mfma<T>::mma(M[(t * STEPS + s) * 64 + lane], bv, acc[t]);
+        }
+        if (valid) {
+#pragma unroll
+            for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    uint32_t osw = out_lane;
+                    if (r >> 1) osw ^= wsw[0];
+#pragma unroll
+                    for (int i = 3; i < KW; ++i)
+                        if (((8 * t) >> i) & 1) osw ^= wsw[i];
+                    T *dst = reinterpret_cast<T *>(cx.lds + (vsw ^ osw) * (uint32_t)sizeof(C));
+                    dst[r & 1] = acc[t][r];
+                }
+        }
+    }
+    lds_barrier();
+    {
+        const uint32_t tsw = swz<C>(cx.tloc) * (uint32_t)sizeof(C);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint32_t kp = 0;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if ((k >> j) & 1) kp |= 1u << rb[j];
+            a[k] = *reinterpret_cast<const C *>(cx.lds + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C))));
+        }
+    }
+    lds_barrier();
+}
+
 // Thread factor of a diagonal-run group, FP64.
 __device__ __forceinline__ double2 k2_group_factor(const svp::DiagGroup &G, const K2Ctx &cx)
 {
@@ -481,6 +604,12 @@ struct K2Interp {
                 k2_layout<LOGR>(a, cx, rb, nrb);
 #pragma unroll
                 for (int j = 0; j < LOGR; ++j) rb[j] = nrb[j];
+            } else if (kind == svp::K2_MFMA) {
+                int wb[5];
+#pragma unroll
+                for (int i = 0; i < 5; ++i) wb[i] = (op.c >> (5 * i)) & 31;
+                if (op.b == 4) k2_mfma<LOGR, 4>(a, cx, rb, wb, l, cx.table + op.a);
+                else k2_mfma<LOGR, 5>(a, cx, rb, wb, l, cx.table + op.a);
             } else if (kind == svp::K2_SCALE) {
                 k2_scale<R>(a, op.v[0]);
             } else if (kind == svp::K2_PHASE) {
