@@ -213,6 +213,12 @@ def install(path: str = MODEL_PATH) -> dict:
 
 # ---------------------------------------------------------------- evaluation
 
+def release() -> None:
+    """Return freed state buffers to the device before the next allocation."""
+    import torch
+    torch.cuda.empty_cache()
+
+
 def evaluate(idxs: Sequence[int], model_path: str, dtype: str = "c64", repeats: int = 3,
              workers: int = 12, paper_l: int = 13) -> dict:
     """Per held-out circuit: exhaustive times of every candidate, the learned
@@ -249,8 +255,10 @@ def evaluate(idxs: Sequence[int], model_path: str, dtype: str = "c64", repeats: 
                 raise
             log(f"eval {i} n={n}: not measured ({e.message})")
             per.append({"circuit": i, "n": n, "learned": li, "not_measured": e.message})
+            release()
             continue
         st.close()
+        release()
         best = int(np.argmin(ms))
         rec = {"circuit": i, "n": n, "ms": ms, "best": best, "learned": li,
                "regret": ms[li] / ms[best] - 1.0, "paper_ms": pms[0],
@@ -271,8 +279,15 @@ def evaluate(idxs: Sequence[int], model_path: str, dtype: str = "c64", repeats: 
 
 
 def _range(spec: str) -> List[int]:
-    a, b = spec.split(":")
-    return list(range(int(a), int(b)))
+    """'a:b' or a comma-separated list of such ranges and single indices."""
+    out = []
+    for part in spec.split(","):
+        if ":" in part:
+            a, b = part.split(":")
+            out += list(range(int(a), int(b)))
+        else:
+            out.append(int(part))
+    return out
 
 
 def main(argv=None) -> int:
@@ -289,6 +304,7 @@ def main(argv=None) -> int:
     e = sub.add_parser("eval")
     e.add_argument("--model", default=MODEL_PATH)
     e.add_argument("--per-n", type=int, default=5)
+    e.add_argument("--circuits", default="", help="explicit eval circuits a:b (instead of --per-n)")
     e.add_argument("--workers", type=int, default=12)
     e.add_argument("--out", required=True)
     a = ap.parse_args(argv)
@@ -308,7 +324,7 @@ def main(argv=None) -> int:
         save(a.out, params, norm, meta)
         log(f"wrote {a.out}: {meta}")
     else:
-        idxs = [10 * k + j for k in range(5) for j in range(a.per_n)]
+        idxs = _range(a.circuits) if a.circuits else [10 * k + j for k in range(5) for j in range(a.per_n)]
         res = evaluate(idxs, a.model, workers=a.workers)
         with open(a.out, "w") as fh:
             json.dump(res, fh, indent=1)

@@ -216,7 +216,10 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
         return fail(SV_ERR_INVALID_ARG, "unknown remap");
     if (s->fuse_k < 0) return fail(SV_ERR_INVALID_ARG, "fuse_k < 0");
     if (s->fuse_k > 6) return fail(SV_ERR_UNSUPPORTED, "fuse_k above 6");
-    if (s->fuse_k > 1) return fail(SV_ERR_UNSUPPORTED, "dense fusion is not available in this build");
+    if (s->fuse_k == 2 || s->fuse_k == 3 || s->fuse_k == 6)
+        return fail(SV_ERR_UNSUPPORTED, "dense fusion windows have 4 or 5 qubits");
+    if (s->fuse_k >= 4 && s->mode != SV_PARTITIONED)
+        return fail(SV_ERR_UNSUPPORTED, "dense fusion runs inside block passes (partitioned mode)");
     if (s->outer_qubits != 0) return fail(SV_ERR_UNSUPPORTED, "outer tier is not available in this build");
     if (s->tuner != SV_TUNER_NONE && s->tuner != SV_TUNER_EXHAUSTIVE && s->tuner != SV_TUNER_LEARNED)
         return fail(SV_ERR_INVALID_ARG, "unknown tuner");

@@ -108,6 +108,14 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
         case svp::K2_SCALE:
             o << "    k2_scale<R>(a, " << hexd(op.v[0]) << ");\n";
             break;
+        case svp::K2_MFMA: {
+            o << "    { const int ro[" << r << "] = {";
+            for (int j = 0; j < r; ++j) o << (j ? ", " : "") << rb[j];
+            o << "}; const int w[5] = {";
+            for (int j = 0; j < 5; ++j) o << (j ? ", " : "") << ((op.c >> (5 * j)) & 31);
+            o << "}; k2_mfma<LOGR, " << op.b << ">(a, cx, ro, w, " << l << ", cx.table + " << op.a << "); }\n";
+            break;
+        }
         case svp::K2_PHASE:
             o << "    k2_phase<R>(a, cx, " << op.a << ", " << (uint32_t)op.m0 << "u, " << u64s(op.m1) << ", mk<C>("
               << hexd(op.v[0]) << ", " << hexd(op.v[1]) << "));\n";

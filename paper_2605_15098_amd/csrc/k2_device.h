@@ -236,7 +236,8 @@ template <> struct K2Mfma<double> {
 // D = 2^(KW+1) on interleaved vectors (real index 2 j + c: amplitude j of
 // the window, component c). Wave-level 16x16x4 MFMA: 16 vectors per group
 // (lane % 16), operand B[k][n] from lane 16 k + n, output D[4 q + r][n] in
-// register r of lane 16 q + n. mat holds M' in A-operand order:
+// register r of lane 16 q + n for FP32, D[4 r + q][n] for FP64 (the FP64
+// instruction interleaves its output rows). mat holds M' in A-operand order:
 // mat[(t * D/4 + s) * 64 + lane] = M'[16 t + lane % 16][4 s + lane / 16].
 // The register layout rb is the same before and after.
 template <int LOGR, int KW, typename C>
@@ -273,11 +274,6 @@ __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const in
     const T *M = static_cast<const T *>(mat);
     // input element of lane: amplitude j = 2 s + (q >> 1), component q & 1
     const uint32_t in_lane = (q >> 1) ? wsw[0] : 0u;
-    // output element of lane: row 16 t + 4 q + r -> amplitude 8 t + 2 q + (r >> 1), component r & 1
-    uint32_t out_lane = 0;
-#pragma unroll
-    for (int i = 0; i < 2 && i + 1 < KW; ++i)
-        if ((q >> i) & 1) out_lane ^= wsw[i + 1];
     for (int g = wave; g < groups; g += nwaves) {
         const uint32_t n = (uint32_t)g * 16u + (uint32_t)col;
         const bool valid = n < nvec;
@@ -307,13 +303,15 @@ __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const in
             for (int t = 0; t < TILES; ++t)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    uint32_t osw = out_lane;
-                    if (r >> 1) osw ^= wsw[0];
+                    // output row of (lane, register): amplitude row >> 1, component row & 1
+                    const int row = 16 * t + (sizeof(T) == 4 ? 4 * q + r : 4 * r + q);
+                    const int jo = row >> 1;
+                    uint32_t osw = 0;
 #pragma unroll
-                    for (int i = 3; i < KW; ++i)
-                        if (((8 * t) >> i) & 1) osw ^= wsw[i];
+                    for (int i = 0; i < KW; ++i)
+                        if ((jo >> i) & 1) osw ^= wsw[i];
                     T *dst = reinterpret_cast<T *>(cx.lds + (vsw ^ osw) * (uint32_t)sizeof(C));
-                    dst[r & 1] = acc[t][r];
+                    dst[row & 1] = acc[t][r];
                 }
         }
     }
@@ -552,7 +550,13 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
             lds_barrier();
         }
 
-        K2Ctx cx{tid, base, tid << 1, lds, ufac, args.table};
+        // The thread index is laundered per block so that the programs' LDS
+        // addresses and per-thread table factors are recomputed for each
+        // block instead of being hoisted out of the block loop, where they
+        // would pin dozens of registers and halve the resident work-groups.
+        uint32_t tid_b = tid;
+        asm volatile("" : "+v"(tid_b));
+        K2Ctx cx{tid_b, base, tid_b << 1, lds, ufac, args.table};
         prog.template run<T, LOGR>(a, cx);
 
         // the program ends in the canonical layout

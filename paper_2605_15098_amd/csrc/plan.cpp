@@ -410,10 +410,121 @@ struct Builder {
             }
             pending.clear();
         };
+        // Dense windows (fuse_k 4 or 5): maximal runs of consecutive gates on
+        // local qubits whose union has at most fuse_k qubits; a run with two
+        // or more gates, at least one of them non-diagonal, becomes one
+        // MFMA op carrying the run's product.
+        std::vector<int> wend(q.size(), -1);
+        std::vector<uint32_t> wbits(q.size(), 0);
+        if (cfg.fuse_k >= 4 && l >= 4) {
+            auto local_bits = [&](const MGate &g) -> int64_t {
+                if (rank[g.t] < 0 || (g.c >= 0 && rank[g.c] < 0)) return -1;
+                uint32_t m = 1u << rank[g.t];
+                if (g.c >= 0) m |= 1u << rank[g.c];
+                return m;
+            };
+            const int kmax = std::min(cfg.fuse_k, l);
+            size_t i = 0;
+            while (i < q.size()) {
+                const int64_t m0 = local_bits(q[i]);
+                if (m0 < 0) {
+                    ++i;
+                    continue;
+                }
+                uint32_t m = (uint32_t)m0;
+                bool dense = q[i].cls != GC_DIAG;
+                size_t e = i + 1;
+                for (; e < q.size(); ++e) {
+                    const int64_t mg = local_bits(q[e]);
+                    if (mg < 0 || __builtin_popcount(m | (uint32_t)mg) > kmax) break;
+                    m |= (uint32_t)mg;
+                    dense = dense || q[e].cls != GC_DIAG;
+                }
+                if (e - i >= 2 && dense) {
+                    wend[i] = (int)e;
+                    wbits[i] = m;
+                }
+                i = e;
+            }
+        }
+        auto emit_mfma = [&](size_t i0, size_t i1, uint32_t m) {
+            std::vector<int> wl;
+            for (int b = 0; b < l; ++b)
+                if ((m >> b) & 1u) wl.push_back(b);
+            const int K = std::max(4, (int)wl.size());
+            for (int b = 0; b < l && (int)wl.size() < K; ++b)
+                if (!((m >> b) & 1u)) wl.push_back(b);
+            std::sort(wl.begin(), wl.end());
+            const int W = 1 << K;
+            auto pos = [&](int memb) {
+                const int lb = rank[memb];
+                for (int i = 0; i < K; ++i)
+                    if (wl[i] == lb) return i;
+                return -1;
+            };
+            // U (row-major, interleaved re/im) = product of the gates, later gates on the left
+            std::vector<double> U(2 * (size_t)W * W, 0.0);
+            for (int x = 0; x < W; ++x) U[2 * ((size_t)x * W + x)] = 1.0;
+            for (size_t gi = i0; gi < i1; ++gi) {
+                const MGate &g = q[gi];
+                const int tp = pos(g.t), cp = g.c >= 0 ? pos(g.c) : -1;
+                for (int col = 0; col < W; ++col)
+                    for (int x = 0; x < W; ++x) {
+                        if ((x >> tp) & 1) continue;
+                        if (cp >= 0 && !((x >> cp) & 1)) continue;
+                        const int y = x | (1 << tp);
+                        double *a = &U[2 * ((size_t)x * W + col)], *b = &U[2 * ((size_t)y * W + col)];
+                        const double ar = a[0], ai = a[1], br = b[0], bi = b[1];
+                        a[0] = g.u[0] * ar - g.u[1] * ai + g.u[2] * br - g.u[3] * bi;
+                        a[1] = g.u[0] * ai + g.u[1] * ar + g.u[2] * bi + g.u[3] * br;
+                        b[0] = g.u[4] * ar - g.u[5] * ai + g.u[6] * br - g.u[7] * bi;
+                        b[1] = g.u[4] * ai + g.u[5] * ar + g.u[6] * bi + g.u[7] * br;
+                    }
+            }
+            // real form: M'[2 jo + co][2 ji + ci]; A-operand order of the
+            // 16x16x4 MFMA: [tile][step][lane] = M'[16 t + lane % 16][4 s + lane / 16]
+            const int D = 2 * W, steps = D / 4, tiles = D / 16;
+            auto mreal = [&](int R, int C) {
+                const double ur = U[2 * ((size_t)(R >> 1) * W + (C >> 1))];
+                const double ui = U[2 * ((size_t)(R >> 1) * W + (C >> 1)) + 1];
+                if ((R & 1) == 0) return (C & 1) ? -ui : ur;
+                return (C & 1) ? ur : ui;
+            };
+            std::vector<double> md((size_t)tiles * steps * 64);
+            for (int t = 0; t < tiles; ++t)
+                for (int st = 0; st < steps; ++st)
+                    for (int lane = 0; lane < 64; ++lane)
+                        md[((size_t)t * steps + st) * 64 + lane] = mreal(16 * t + lane % 16, 4 * st + lane / 16);
+            K2Op op{};
+            op.kind = K2_MFMA;
+            if (cfg.dtype == 0) {
+                std::vector<float> mf(md.begin(), md.end());
+                op.a = table_put(mf.data(), mf.size() * sizeof(float));
+            } else {
+                op.a = table_put(md.data(), md.size() * sizeof(double));
+            }
+            op.b = K;
+            int packed = 0;
+            uint64_t mask = 0;
+            for (int i = 0; i < K; ++i) {
+                packed |= wl[i] << (5 * i);
+                mask |= 1ull << wl[i];
+            }
+            op.c = packed;
+            op.m0 = mask;
+            plan.ops.push_back(op);
+            plan.stats.fused += (int64_t)(i1 - i0);
+        };
         int hscale = 0;  // unnormalized Hadamards applied in this pass
         const int begin = (int)plan.ops.size();
         for (size_t i = 0; i < q.size(); ++i) {
             const MGate &g = q[i];
+            if (wend[i] > 0) {
+                flush_diag();
+                emit_mfma(i, (size_t)wend[i], wbits[i]);
+                i = (size_t)wend[i] - 1;
+                continue;
+            }
             if (g.cls == GC_DIAG) {
                 pending.push_back(g);
                 continue;

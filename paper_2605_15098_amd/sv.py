@@ -495,9 +495,11 @@ class StateVector:
         return sv_layout(self.h, self.n)
 
     def close(self):
+        """Destroy the handle and drop the device buffer."""
         if getattr(self, "h", None):
             sv_destroy(self.h)
             self.h = None
+        self.tensor = None
 
     def __del__(self):
         try:

@@ -43,6 +43,7 @@ cd expturn(uint64_t a)
 }
 
 bool return_error = false;
+int g_dtype = 0;  // dtype of the plan being emulated (table precision)
 
 void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
 {
@@ -176,6 +177,52 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
             } else if (op.kind == K2_SCALE) {
                 for (int tid = 0; tid < NT; ++tid)
                     for (int k = 0; k < R; ++k) a[tid][k] *= op.v[0];
+            } else if (op.kind == K2_MFMA) {
+                // unpack the operand-ordered real matrix and apply it to every
+                // vector of the window bits, in FP64
+                const int K = op.b, W = 1 << K, D = 2 * W, steps = D / 4;
+                std::vector<int> w(K);
+                uint32_t wm = 0;
+                for (int i = 0; i < K; ++i) {
+                    w[i] = (op.c >> (5 * i)) & 31;
+                    wm |= 1u << w[i];
+                }
+                if ((uint64_t)wm != op.m0) return_error = true;
+                std::vector<double> M((size_t)D * D);
+                for (int t = 0; t < D / 16; ++t)
+                    for (int s = 0; s < steps; ++s)
+                        for (int lane = 0; lane < 64; ++lane) {
+                            const size_t idx = ((size_t)t * steps + s) * 64 + lane;
+                            const double v = g_dtype == 0 ? (double)reinterpret_cast<const float *>(table + op.a)[idx]
+                                                          : reinterpret_cast<const double *>(table + op.a)[idx];
+                            M[(size_t)(16 * t + lane % 16) * D + 4 * s + lane / 16] = v;
+                        }
+                for (int tid = 0; tid < NT; ++tid)
+                    for (int k = 0; k < R; ++k) lds[amp_loc(tid, k)] = a[tid][k];
+                for (uint32_t v = 0; v < (1u << (l - K)); ++v) {
+                    uint32_t vb = 0, mm = v;
+                    for (int b = 0; b < l; ++b)
+                        if (!((wm >> b) & 1u)) {
+                            vb |= (mm & 1u) << b;
+                            mm >>= 1;
+                        }
+                    auto addr = [&](int j) {
+                        uint32_t x = vb;
+                        for (int i = 0; i < K; ++i)
+                            if ((j >> i) & 1) x |= 1u << w[i];
+                        return x;
+                    };
+                    std::vector<double> in(D), out(D, 0.0);
+                    for (int j = 0; j < W; ++j) {
+                        in[2 * j] = lds[addr(j)].real();
+                        in[2 * j + 1] = lds[addr(j)].imag();
+                    }
+                    for (int rr = 0; rr < D; ++rr)
+                        for (int cc = 0; cc < D; ++cc) out[rr] += M[(size_t)rr * D + cc] * in[cc];
+                    for (int j = 0; j < W; ++j) lds[addr(j)] = cd(out[2 * j], out[2 * j + 1]);
+                }
+                for (int tid = 0; tid < NT; ++tid)
+                    for (int k = 0; k < R; ++k) a[tid][k] = lds[amp_loc(tid, k)];
             } else {
                 const int J = op.a, H = 1 << J;
                 const cd u00(op.v[0], op.v[1]), u01(op.v[2], op.v[3]), u10(op.v[4], op.v[5]),
@@ -217,6 +264,7 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
                          int64_t *counts_out)
 {
     PlanConfig c;
+    g_dtype = dtype;
     c.n = n;
     c.dtype = dtype;
     c.mode = mode;

@@ -58,9 +58,17 @@ def test_unknown_op_and_swap_with_control():
 
 def test_schedule_errors():
     g = W.qpe_gates(6, 0.25)
+    for fk in (2, 3, 6, 7):
+        with pytest.raises(sv.SvError) as e:
+            sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=fk))
+        assert e.value.status == sv.SV_ERR_UNSUPPORTED
     with pytest.raises(sv.SvError) as e:
-        sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=7))
+        sv.sv_plan(6, "c64", g, sv.schedule("plain", fuse_k=5))
     assert e.value.status == sv.SV_ERR_UNSUPPORTED
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=-1))
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
+    assert sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=5))["fused"] > 0
     with pytest.raises(sv.SvError) as e:
         sv.sv_plan(6, "c64", g, sv.schedule(block_qubits=15))
     assert e.value.status == sv.SV_ERR_UNSUPPORTED

@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 from oracle import qpe as cf
+from paper_2605_15098_amd import sv
 from paper_2605_15098_amd import workloads as W
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -133,8 +134,31 @@ def test_non_unit_diagonal_u2():
     assert np.max(np.abs(got - want)) < 1e-12
 
 
+@pytest.mark.parametrize("fuse", [4, 5])
+@pytest.mark.parametrize("n,l,dtype", [(6, 4, 1), (6, 5, 1), (10, 6, 1), (12, 9, 0), (13, 13, 1), (14, 10, 0)])
+def test_dense_fusion_programs(n, l, dtype, fuse):
+    """Windows of up to `fuse` qubits as one matrix op (the emulator applies
+    the operand-ordered table in FP64): complex128 tables hold the FP64
+    product, complex64 tables its FP32 rounding."""
+    if fuse > l:
+        pytest.skip("window larger than the block")
+    rng = np.random.default_rng(n * 10 + l + fuse)
+    tol = 1e-12 if dtype == 1 else 1e-6
+    g = W.random_mixed_circuit(n, 120, rng)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    got, _ = run(n, g, psi0, dtype=dtype, l=l, fuse=fuse)
+    assert np.max(np.abs(got - oracle.apply(n, g, psi0))) < tol
+    phi = W.phi_for_seed(n)
+    got, _ = run(n, W.qpe_gates(n, phi), dtype=dtype, l=l, fuse=fuse)
+    assert np.max(np.abs(got - cf.qpe_state(n, phi))) < tol
+    st = sv.sv_plan(n, "c64" if dtype == 0 else "c128", W.qpe_gates(n, phi),
+                    sv.schedule(block_qubits=l, fuse_k=fuse))
+    assert st["fused"] > 0
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
-@pytest.mark.parametrize("case", ["qpe", "random", "diag", "strict"])
+@pytest.mark.parametrize("case", ["qpe", "random", "diag", "strict", "fused"])
 def test_generated_pass_kernels_compile(case, dtype):
     """Every block-pass kernel the run-time compiler writes must compile for
     gfx950 (hipRTC runs without a GPU)."""
@@ -147,6 +171,9 @@ def test_generated_pass_kernels_compile(case, dtype):
     elif case == "diag":
         g = W.random_circuit(n, 150, rng)
         logr = 5 if dtype == 0 else 3
+    elif case == "fused":
+        g = W.random_mixed_circuit(n, 120, rng)
+        fuse = 5
     else:
         g = W.random_mixed_circuit(n, 60, rng)
         fuse = 0
