@@ -239,7 +239,8 @@ template <> struct K2Mfma<double> {
 // register r of lane 16 q + n for FP32, D[4 r + q][n] for FP64 (the FP64
 // instruction interleaves its output rows). mat holds M' in A-operand order:
 // mat[(t * D/4 + s) * 64 + lane] = M'[16 t + lane % 16][4 s + lane / 16].
-// The register layout rb is the same before and after.
+// The register layout rb is the same before and after. Needs full waves
+// (2^(l - LOGR) >= 64 threads).
 template <int LOGR, int KW, typename C>
 __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const int *w, int l, const void *mat)
 {
@@ -260,8 +261,10 @@ __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const in
         }
     }
     lds_barrier();
+    // whole waves only: the planner emits this op for blocks of 64 or more
+    // threads (every lane supplies an operand)
     const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
-    const int nwaves = (int)(blockDim.x >> 6);
+    const int nwaves = blockDim.x >= 64u ? (int)(blockDim.x >> 6) : 1;
     const int col = lane & 15, q = lane >> 4;
     uint32_t wsw[KW], wmask = 0;
 #pragma unroll

@@ -416,7 +416,8 @@ struct Builder {
         // MFMA op carrying the run's product.
         std::vector<int> wend(q.size(), -1);
         std::vector<uint32_t> wbits(q.size(), 0);
-        if (cfg.fuse_k >= 4 && l >= 4) {
+        // the matrix-core op needs whole waves: 64 or more threads per block
+        if (cfg.fuse_k >= 4 && l >= 4 && l - logr >= 6) {
             auto local_bits = [&](const MGate &g) -> int64_t {
                 if (rank[g.t] < 0 || (g.c >= 0 && rank[g.c] < 0)) return -1;
                 uint32_t m = 1u << rank[g.t];
