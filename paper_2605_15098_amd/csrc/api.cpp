@@ -1205,6 +1205,8 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
                     if (rec->g.wave_off >= 0) rec->g.wave_off += (int)tb;
                     rec->pad = 1;  // rebased
                 }
+            } else if (op.kind == svp::K2_MFMA) {
+                op.a += (int)tb;
             }
             ops.push_back(op);
         }
