@@ -314,6 +314,10 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
             a.nops = s.op_count;
             a.nug = s.nug;
             a.ug_off = s.ug_off;
+            a.tab_off = s.tab_off;
+            a.tab_count = s.tab_count;
+            a.ut_off = s.ut_off;
+            a.nut = s.nut;
             a.table = h->dtab;
             a.vec2 = (s.l >= 2 && s.logr >= 2 && s.bits[0] == 0) ? 1 : 0;
             std::vector<bool> in(h->n, false);
@@ -1189,7 +1193,8 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     std::vector<svp::BatchPass> passes;
     std::vector<svp::BatchInst> insts(count);
     std::vector<double> work(count);
-    int max_nug = 0;
+    size_t max_lds = 0;
+    const size_t amp = dtype == 0 ? 8 : 16;
     for (int i = 0; i < count; ++i) {
         const svp::Plan &P = plans[i];
         const size_t tb = align16(table.size());
@@ -1199,12 +1204,6 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
         for (svp::K2Op op : P.ops) {
             if (op.kind == svp::K2_DIAGRUN) {
                 op.a += (int)tb;
-                svp::DiagRec *rec = reinterpret_cast<svp::DiagRec *>(table.data() + op.a);
-                if (rec->has_group && rec->pad == 0) {
-                    if (rec->g.lane_off >= 0) rec->g.lane_off += (int)tb;
-                    if (rec->g.wave_off >= 0) rec->g.wave_off += (int)tb;
-                    rec->pad = 1;  // rebased
-                }
             } else if (op.kind == svp::K2_MFMA) {
                 op.a += (int)tb;
             }
@@ -1221,6 +1220,11 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
             bp.args.nops = st.op_count;
             bp.args.nug = st.nug;
             bp.args.ug_off = st.nug ? (int)(st.ug_off + tb) : 0;
+            bp.args.tab_off = st.tab_count ? (int)(st.tab_off + tb) : 0;
+            bp.args.tab_count = st.tab_count;
+            bp.args.ut_off = st.nut ? (int)(st.ut_off + tb) : 0;
+            bp.args.nut = st.nut;
+            max_lds = std::max<size_t>(max_lds, svp::k2_lds_layout(st.l, (int)amp, st.nug, st.tab_count, st.nut).total);
             bp.args.vec2 = (st.l >= 2 && st.logr >= 2 && st.bits[0] == 0) ? 1 : 0;
             std::vector<bool> in(hs[i]->n, false);
             for (int b = 0; b < st.l; ++b) {
@@ -1231,11 +1235,6 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
             for (int p = 0; p < hs[i]->n; ++p)
                 if (!in[p]) bp.args.nbits[k++] = (int8_t)p;
             bp.op_begin = ob + st.op_begin;
-            if (st.nug) {
-                svp::UGroup *ug = reinterpret_cast<svp::UGroup *>(table.data() + bp.args.ug_off);
-                for (int g = 0; g < st.nug; ++g) ug[g].term_off += (int)tb;
-            }
-            max_nug = std::max(max_nug, st.nug);
             passes.push_back(bp);
             insts[i].npass += 1;
         }
@@ -1243,8 +1242,7 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     }
     // resident capacity and work-group groups
     const unsigned threads = 1u << (l - logr);
-    const size_t amp = dtype == 0 ? 8 : 16;
-    const size_t lds = (amp << l) + (size_t)max_nug * 16;
+    const size_t lds = std::max<size_t>(max_lds, svp::k2_lds_layout(l, (int)amp, 0, 0, 0).total);
     const int per_cu = svk::k6_occupancy(dtype, logr, threads, lds);
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

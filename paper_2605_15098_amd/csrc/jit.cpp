@@ -88,19 +88,20 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
         case svp::K2_DIAGRUN: {
             const svp::DiagRec *rec = reinterpret_cast<const svp::DiagRec *>(plan.table.data() + op.a);
             const double *qt = reinterpret_cast<const double *>(rec + 1);
-            o << "    {\n      double2 f = make_double2(1.0, 0.0);\n";
+            o << "    {\n";
             if (rec->has_group) {
                 const svp::DiagGroup &G = rec->g;
                 o << "      const svp::DiagGroup G{" << G.rmask << ", " << G.cond_kind << ", " << G.cond_bit << ", "
                   << G.uidx << ", " << G.lane_off << ", " << G.wave_off << ", 0, 0};\n"
-                  << "      f = k2_group_factor(G, cx);\n";
+                  << "      const C fc = k2_group_factor<C>(G, cx);\n";
+            } else {
+                o << "      const C fc = mk<C>(1.0, 0.0);\n";
             }
-            o << "      const C fc = mk<C>(f.x, f.y);\n";
             for (int k = 0; k < R; ++k) {
                 if (!((rec->kmask >> k) & 1u)) continue;
                 const bool q = (rec->qmask >> k) & 1u;
                 o << "      k2_diag_amp(a[" << k << "], " << (q ? "true" : "false") << ", make_double2("
-                  << hexd(qt[2 * k]) << ", " << hexd(qt[2 * k + 1]) << "), f, fc);\n";
+                  << hexd(qt[2 * k]) << ", " << hexd(qt[2 * k + 1]) << "), fc);\n";
             }
             o << "    }\n";
             break;
@@ -139,13 +140,15 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
     }
     o << "  }\n};\n";
     const char *T = dtype == 0 ? "float" : "double";
+    const bool vec2 = s.l >= 2 && s.logr >= 2 && s.bits[0] == 0;  // as the launcher sets args.vec2
     const unsigned threads = 1u << (l - r);
     const size_t amp = dtype == 0 ? 8 : 16;
-    const size_t lds = ((amp << l) + (size_t)s.nug * 16 + 15) / 16 * 16;
+    const size_t lds = svp::k2_lds_layout(l, (int)amp, s.nug, s.tab_count, s.nut).total;
     o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") svk2_pass_" << idx << "(CT<" << T
       << ">::type *__restrict__ S, svp::K2Args args) {\n"
       << "  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[" << (lds > 0 ? lds : 16) << "];\n"
-      << "  k2_body<" << T << ", " << r << ">(S, args, lds_raw, Prog" << idx << "{}, blockIdx.x, gridDim.x);\n}\n";
+      << "  k2_body<" << T << ", " << r << ", " << (vec2 ? "true" : "false") << ">(S, args, lds_raw, Prog" << idx
+      << "{}, blockIdx.x, gridDim.x);\n}\n";
     return o.str();
 }
 

@@ -54,8 +54,8 @@ struct DiagGroup {
     int32_t cond_kind;  // 0 none, 1 memory bit of the block base, 2 thread-id bit (>= 6)
     int32_t cond_bit;
     int32_t uidx;       // block-uniform factor index, -1 none
-    int32_t lane_off;   // byte offset of 64 complex doubles, -1 none
-    int32_t wave_off;   // byte offset of 2^(waves) complex doubles, -1 none
+    int32_t lane_off;   // index of 64 entries in the pass's factor table, -1 none
+    int32_t wave_off;   // index of 2^(waves) entries in that table, -1 none
     int32_t pad0, pad1;
 };
 
@@ -74,7 +74,7 @@ struct DiagRec {
 // Block-uniform factor: e^{2 pi i sum angle_j [base covers tmask_j]} with
 // angles as 64-bit fixed-point turns; computed once per block.
 struct UGroup {
-    int32_t term_off;   // byte offset of the UTerm array
+    int32_t term_off;   // index of the group's first term in the pass's UTerm array
     int32_t nterms;
 };
 struct UTerm {
@@ -93,7 +93,32 @@ struct K2Args {
     int32_t vec2;              // 1: memory bit 0 is local bit 0 (16-byte complex64 pairs)
     int8_t bits[48];           // memory bit of each local bit, ascending
     int8_t nbits[48];          // memory bits outside the block, ascending
+    int32_t tab_off;           // byte offset of the pass's lane/wave factor
+    int32_t tab_count;         // table (tab_count complex doubles), staged in LDS
+    int32_t ut_off;            // byte offset of the pass's UTerm array
+    int32_t nut;               // its length (staged in LDS with the UGroups)
 };
+
+// LDS of a block pass, in this order (16-byte aligned pieces): the block
+// (2^l amplitudes), nug block-uniform factors (double2), the lane/wave factor
+// table (tab_count amplitudes), nut UTerms, nug UGroups.
+struct K2Lds {
+    uint32_t ufac, tabs, uterm, ugrp, total;
+};
+#if defined(__HIPCC_RTC__) || defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+__host__ __device__
+#endif
+inline K2Lds k2_lds_layout(int l, int amp, int nug, int tab_count, int nut)
+{
+    auto up = [](uint32_t x) { return (x + 15u) & ~15u; };
+    K2Lds o;
+    o.ufac = up((uint32_t)amp << l);
+    o.tabs = up(o.ufac + 16u * (uint32_t)nug);
+    o.uterm = up(o.tabs + (uint32_t)amp * (uint32_t)tab_count);
+    o.ugrp = up(o.uterm + 16u * (uint32_t)nut);
+    o.total = up(o.ugrp + 8u * (uint32_t)nug);
+    return o;
+}
 
 // Batched passes (one persistent launch over many states). Instance i is
 // served by work-groups group_off .. group_off + group_size - 1, which run its

@@ -171,6 +171,7 @@ struct K2Ctx {
     unsigned char *lds;          // block buffer for re-layouts
     const double2 *ufac;         // block-uniform factors
     const unsigned char *table;  // plan table
+    const unsigned char *tabs;   // the pass's lane/wave factors in LDS (type C)
 };
 
 // Re-layout through LDS: the amplitudes leave registers in layout rb_old and
@@ -333,31 +334,34 @@ __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const in
     lds_barrier();
 }
 
-// Thread factor of a diagonal-run group, FP64.
-__device__ __forceinline__ double2 k2_group_factor(const svp::DiagGroup &G, const K2Ctx &cx)
+// Thread factor of a diagonal-run group: block-uniform factor (FP64, cast
+// once) times the wave and lane entries of the pass's factor table in LDS,
+// in the state's precision.
+template <typename C>
+__device__ __forceinline__ C k2_group_factor(const svp::DiagGroup &G, const K2Ctx &cx)
 {
-    double2 f = make_double2(1.0, 0.0);
+    // keeps the scheduler from starting many runs' factors at once, which
+    // would raise register use past the two-work-groups-per-CU budget
+    __builtin_amdgcn_sched_barrier(0);
+    C f = mk<C>(1.0, 0.0);
     bool on = true;
     if (G.cond_kind == 1) on = (cx.base >> G.cond_bit) & 1ull;
     else if (G.cond_kind == 2) on = (cx.tid >> G.cond_bit) & 1u;
     if (on) {
-        if (G.uidx >= 0) f = cx.ufac[G.uidx];
-        if (G.wave_off >= 0) f = cmul(f, reinterpret_cast<const double2 *>(cx.table + G.wave_off)[cx.tid >> 6]);
-        if (G.lane_off >= 0) f = cmul(f, reinterpret_cast<const double2 *>(cx.table + G.lane_off)[cx.tid & 63u]);
+        const C *tab = reinterpret_cast<const C *>(cx.tabs);
+        if (G.uidx >= 0) f = mk<C>(cx.ufac[G.uidx].x, cx.ufac[G.uidx].y);
+        if (G.wave_off >= 0) f = cmul(f, tab[G.wave_off + (cx.tid >> 6)]);
+        if (G.lane_off >= 0) f = cmul(f, tab[G.lane_off + (cx.tid & 63u)]);
     }
     return f;
 }
 
-// One amplitude of a diagonal run: times f, or times Q[k] * f (FP64, rounded
-// once) when the slot has a constant factor.
+// One amplitude of a diagonal run: times the group factor fc, or times
+// Q[k] * fc when the slot has a constant factor.
 template <typename C>
-__device__ __forceinline__ void k2_diag_amp(C &ak, bool with_q, double2 q, double2 f, C fc)
+__device__ __forceinline__ void k2_diag_amp(C &ak, bool with_q, double2 q, C fc)
 {
-    C Fk = fc;
-    if (with_q) {
-        const double2 F = cmul(q, f);
-        Fk = mk<C>(F.x, F.y);
-    }
+    const C Fk = with_q ? cmul(mk<C>(q.x, q.y), fc) : fc;
     ak = cmul(Fk, ak);
 }
 
@@ -366,13 +370,11 @@ __device__ __forceinline__ void k2_diagrun(C *a, const K2Ctx &cx, const svp::Dia
 {
     const double2 *qt = reinterpret_cast<const double2 *>(rec + 1);
     const uint32_t kmask = rec->kmask, qmask = rec->qmask;
-    double2 f = make_double2(1.0, 0.0);
-    if (rec->has_group) f = k2_group_factor(rec->g, cx);
-    const C fc = mk<C>(f.x, f.y);
+    const C fc = rec->has_group ? k2_group_factor<C>(rec->g, cx) : mk<C>(1.0, 0.0);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         if (!((kmask >> k) & 1u)) continue;
-        k2_diag_amp(a[k], ((qmask >> k) & 1u) != 0, qt[k], f, fc);
+        k2_diag_amp(a[k], ((qmask >> k) & 1u) != 0, qt[k], fc);
     }
 }
 
@@ -428,11 +430,16 @@ template <typename T, int LOGR> constexpr int k2_max_threads()
 }
 
 // Memory bits outside the block, from the block number (work-group uniform).
-__device__ __forceinline__ uint64_t k2_base(uint64_t bid, const svp::K2Args &args)
+// Deposit the low bits of v at the set bits of mask, in ascending order. With
+// v and mask uniform this stays on the scalar unit.
+__device__ __forceinline__ uint64_t k2_deposit(uint64_t v, uint64_t mask)
 {
-    uint64_t base = 0;
-    for (int i = 0; i < args.n - args.l; ++i) base |= ((bid >> i) & 1ull) << args.nbits[i];
-    return uniform64(base);
+    uint64_t out = 0;
+    for (uint64_t m = mask; m != 0; m &= m - 1) {
+        if (v & 1ull) out |= m & (~m + 1ull);
+        v >>= 1;
+    }
+    return out;
 }
 
 template <int LOGR, typename C>
@@ -502,8 +509,12 @@ __device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t
 // threadIdx. A program starts and ends in the canonical layout: slot 0 =
 // local bit 0, slots 1.. = the top LOGR-1 local bits, so lanes walk
 // consecutive memory and, for complex64, slots 0 and 1 form one 16-byte
-// access. lds must hold 2^l amplitudes followed by args.nug double2.
-template <typename T, int LOGR, class Prog>
+// access. lds is laid out by k2_lds_layout.
+//
+// V2 must equal args.vec2: a compile-time access width keeps one load path in
+// the loop, so the wait for the current block counts only its own loads and
+// the next block's prefetch stays in flight.
+template <typename T, int LOGR, bool V2, class Prog>
 __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
                                         unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
 {
@@ -513,8 +524,16 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     const int tb = l - LOGR;
     const uint32_t tid = threadIdx.x;
     const uint64_t nblocks = 1ull << (args.n - l);
-    const bool vec2 = args.vec2 != 0;
-    double2 *ufac = reinterpret_cast<double2 *>(lds + (sizeof(C) << l));
+    constexpr bool vec2 = V2;
+    const svp::K2Lds L = svp::k2_lds_layout(l, (int)sizeof(C), args.nug, args.tab_count, args.nut);
+    double2 *ufac = reinterpret_cast<double2 *>(lds + L.ufac);
+    C *tabs = reinterpret_cast<C *>(lds + L.tabs);
+    svp::UTerm *uterm = reinterpret_cast<svp::UTerm *>(lds + L.uterm);
+    svp::UGroup *ugrp = reinterpret_cast<svp::UGroup *>(lds + L.ugrp);
+    // memory bits outside the block, as a mask (the block number is deposited there)
+    uint64_t gmask = 0;
+    for (int i = 0; i < args.n - l; ++i) gmask |= 1ull << args.nbits[i];
+    gmask = uniform64(gmask);
 
     // canonical-layout addressing, the same for every block
     uint64_t tmem_local = 0;
@@ -526,25 +545,40 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
 
     uint64_t bid = first;
     if (bid >= nblocks) return;
-    uint64_t base = k2_base(bid, args);
+    // the pass's lane/wave factors, once per launch: LDS reads keep the
+    // program clear of vector-memory waits, which would also wait for the
+    // next block's prefetch
+    // (the block-uniform terms likewise)
+    if (args.tab_count > 0 || args.nug > 0) {
+        const double2 *src = reinterpret_cast<const double2 *>(args.table + args.tab_off);
+        for (int i = (int)tid; i < args.tab_count; i += (int)blockDim.x) tabs[i] = mk<C>(src[i].x, src[i].y);
+        const svp::UTerm *ts = reinterpret_cast<const svp::UTerm *>(args.table + args.ut_off);
+        for (int i = (int)tid; i < args.nut; i += (int)blockDim.x) uterm[i] = ts[i];
+        const svp::UGroup *gs = reinterpret_cast<const svp::UGroup *>(args.table + args.ug_off);
+        for (int i = (int)tid; i < args.nug; i += (int)blockDim.x) ugrp[i] = gs[i];
+        __syncthreads();
+    }
+    uint64_t base = uniform64(k2_deposit(bid, gmask));
     C a[R], b[R];
     k2_load<LOGR>(a, S, base | tmem_local, roff, vec2);
 
     for (;;) {
         const uint64_t next = bid + stride;
         const bool has_next = next < nblocks;
-        const uint64_t nbase = has_next ? k2_base(next, args) : 0ull;
-        if (has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
+        // The prefetch is issued on every iteration (the last one re-reads
+        // the current block): with a path-independent count of loads in
+        // flight, the wait for this block's data does not also wait for it.
+        const uint64_t nbase = has_next ? uniform64(k2_deposit(next, gmask)) : base;
+        k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
 
         // Block-uniform phase factors of the diagonal runs: each is
         // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in
         // 64-bit fixed-point turns and evaluated once per block.
         if (args.nug > 0) {
-            const svp::UGroup *ug = reinterpret_cast<const svp::UGroup *>(args.table + args.ug_off);
             for (int g = threadIdx.x; g < args.nug; g += blockDim.x) {
-                const svp::UTerm *tm = reinterpret_cast<const svp::UTerm *>(args.table + ug[g].term_off);
+                const svp::UTerm *tm = uterm + ugrp[g].term_off;
                 uint64_t acc = 0;
-                for (int j = 0; j < ug[g].nterms; ++j)
+                for (int j = 0; j < ugrp[g].nterms; ++j)
                     if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
                 double sn, cs;
                 sincospi(ldexp((double)(int64_t)acc, -63), &sn, &cs);
@@ -559,7 +593,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         // would pin dozens of registers and halve the resident work-groups.
         uint32_t tid_b = tid;
         asm volatile("" : "+v"(tid_b));
-        K2Ctx cx{tid_b, base, tid_b << 1, lds, ufac, args.table};
+        K2Ctx cx{tid_b, base, tid_b << 1, lds, ufac, args.table, reinterpret_cast<const unsigned char *>(tabs)};
         prog.template run<T, LOGR>(a, cx);
 
         // the program ends in the canonical layout
@@ -571,6 +605,15 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         base = nbase;
         bid = next;
     }
+}
+
+// k2_body with the access width chosen once, outside the block loop.
+template <typename T, int LOGR, class Prog>
+__device__ __forceinline__ void k2_body_any(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
+                                            unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
+{
+    if (args.vec2) k2_body<T, LOGR, true>(S, args, lds, prog, first, stride);
+    else k2_body<T, LOGR, false>(S, args, lds, prog, first, stride);
 }
 
 // ------------------------------------------------------------ interpreter

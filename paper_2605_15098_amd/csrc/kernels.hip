@@ -194,7 +194,7 @@ __global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
 k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, svp::K2Args args)
 {
     extern __shared__ unsigned char lds_raw[];
-    k2_body<T, LOGR>(S, args, lds_raw, K2Interp{ops, args.nops, args.l}, blockIdx.x, gridDim.x);
+    k2_body_any<T, LOGR>(S, args, lds_raw, K2Interp{ops, args.nops, args.l}, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- k6
@@ -243,7 +243,7 @@ k6_batch_kernel(const svp::BatchInst *__restrict__ insts, const int32_t *__restr
     const uint64_t rank = blockIdx.x - I.group_off;
     for (int p = 0; p < I.npass; ++p) {
         const svp::BatchPass &P = passes[I.pass_off + p];
-        k2_body<T, LOGR>((C *)I.S, P.args, lds_raw, K2Interp{ops + P.op_begin, P.args.nops, P.args.l}, rank,
+        k2_body_any<T, LOGR>((C *)I.S, P.args, lds_raw, K2Interp{ops + P.op_begin, P.args.nops, P.args.l}, rank,
                          (uint64_t)I.group_size);
         if (I.group_size > 1 && p + 1 < I.npass)
             if (!group_barrier(&ctrs[I.ctr], (unsigned)((p + 1) * I.group_size), err, limit, &ok)) return;
@@ -308,7 +308,7 @@ template <typename T, int LOGR>
 static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hipStream_t st)
 {
     using C = typename CT<T>::type;
-    const size_t lds = ((size_t)sizeof(C) << a.l) + (size_t)a.nug * sizeof(double2);
+    const size_t lds = svp::k2_lds_layout(a.l, (int)sizeof(C), a.nug, a.tab_count, a.nut).total;
     static size_t attr_bytes = 64 * 1024;
     if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k2_kernel<T, LOGR>,

@@ -138,6 +138,10 @@ struct Builder {
 
     // ---- block-pass compilation ---------------------------------------
 
+    // Lane/wave factor tables of the pass being compiled (re, im pairs);
+    // stored once per pass and staged into LDS by the kernel.
+    std::vector<double> ptab;
+
     // Append raw bytes to the table buffer at a 16-byte aligned offset.
     int table_put(const void *p, size_t bytes)
     {
@@ -266,7 +270,9 @@ struct Builder {
                 }
                 cexp(acc, &tab[2 * x]);
             }
-            return table_put(tab.data(), tab.size() * sizeof(double));
+            const int idx = (int)(ptab.size() / 2);
+            ptab.insert(ptab.end(), tab.begin(), tab.end());
+            return idx;
         };
         // One op per factor group; constant factors ride with the first op
         // whose group covers their slots, the rest get an op of their own.
@@ -328,6 +334,7 @@ struct Builder {
     {
         const int r = logr;
         const bool combine = cfg.fuse_k >= 1;
+        ptab.clear();
         std::vector<int> rank(64, -1);
         for (int i = 0; i < (int)B.size(); ++i) rank[B[i]] = i;
         // canonical layout (load and store): slot 0 = local bit 0, the other
@@ -584,10 +591,13 @@ struct Builder {
         s.op_begin = begin;
         s.op_count = (int)plan.ops.size() - begin;
         s.ngates = (int)q.size();
+        if (!ptab.empty()) {
+            s.tab_off = table_put(ptab.data(), ptab.size() * sizeof(double));
+            s.tab_count = (int)(ptab.size() / 2);
+        }
         if (!ugroups.empty()) {
-            // term offsets become byte offsets in the table
-            const int toff = table_put(uterms.data(), uterms.size() * sizeof(UTerm));
-            for (UGroup &u : ugroups) u.term_off = toff + u.term_off * (int)sizeof(UTerm);
+            s.ut_off = table_put(uterms.data(), uterms.size() * sizeof(UTerm));
+            s.nut = (int)uterms.size();
             s.ug_off = table_put(ugroups.data(), ugroups.size() * sizeof(UGroup));
             s.nug = (int)ugroups.size();
         }

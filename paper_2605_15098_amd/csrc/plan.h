@@ -63,6 +63,8 @@ struct Step {
     int bits[64] = {0};     // ST_K2: memory bit of each local bit (ascending)
     int op_begin = 0, op_count = 0;
     int ug_off = 0, nug = 0;  // ST_K2: block-uniform factor groups
+    int tab_off = 0, tab_count = 0;  // ST_K2: lane/wave factor table (complex doubles)
+    int ut_off = 0, nut = 0;         // ST_K2: UTerm array of the block-uniform groups
     int p = 0, v = 0;       // ST_K3
     int ngates = 0;         // gates applied by this step
 };

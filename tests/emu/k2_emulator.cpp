@@ -65,7 +65,7 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
         std::vector<cd> ufac(st.nug);
         for (int g = 0; g < st.nug; ++g) {
             const UGroup *ug = reinterpret_cast<const UGroup *>(table + st.ug_off) + g;
-            const UTerm *tm = reinterpret_cast<const UTerm *>(table + ug->term_off);
+            const UTerm *tm = reinterpret_cast<const UTerm *>(table + st.ut_off) + ug->term_off;
             uint64_t acc = 0;
             for (int j = 0; j < ug->nterms; ++j)
                 if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
@@ -154,12 +154,13 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
                         else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1;
                         if (on) {
                             if (G.uidx >= 0) f = ufac[G.uidx];
+                            const double *ptab = reinterpret_cast<const double *>(table + st.tab_off);
                             if (G.wave_off >= 0) {
-                                const double *w = reinterpret_cast<const double *>(table + G.wave_off);
+                                const double *w = ptab + 2 * G.wave_off;
                                 f *= cd(w[2 * (tid >> 6)], w[2 * (tid >> 6) + 1]);
                             }
                             if (G.lane_off >= 0) {
-                                const double *w = reinterpret_cast<const double *>(table + G.lane_off);
+                                const double *w = ptab + 2 * G.lane_off;
                                 f *= cd(w[2 * (tid & 63)], w[2 * (tid & 63) + 1]);
                             }
                         }
