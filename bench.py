@@ -33,7 +33,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "plan.cpp", "plan.h"):
+    for f in ("kernels.hip", "k2_device.h", "k2_abi.h", "jit.cpp", "plan.cpp", "plan.h"):
         with open(os.path.join(ROOT, "paper_2605_15098_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -201,6 +201,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--quick", action="store_true", help="skip comparison runs and CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain 4 GiB read + 4 GiB write kernel "
+                         "(the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the build has no multi-GPU path); got --gpus {args.gpus}",
@@ -276,6 +279,16 @@ def main():
         "parity": check,
     }
 
+    if args.copy_calibration:
+        # one elementwise kernel that reads 4 GiB and writes 4 GiB: the
+        # reference against which HBM byte counters are scaled
+        src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     if not args.quick:
         comps = {}
         for name, dt, sch, st_, wu in (
