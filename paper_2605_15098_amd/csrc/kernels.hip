@@ -590,19 +590,41 @@ hipError_t argmax(const double *p, uint64_t len, void *scratch, uint64_t *res_id
     return hipGetLastError();
 }
 
+// The marginal's physical bits in ascending order, as runs of consecutive
+// bits (a permuted layout usually leaves one or two), and the logical bit of
+// each: the marginal is walked in memory order so that neighbouring threads
+// read neighbouring amplitudes, and the logical index is formed only for
+// entries that can win.
+struct PhysMarg {
+    int8_t src[48], dst[48], len[48];  // run r: bits src..src+len-1 of p -> dst..
+    int8_t lbit[48];                   // logical bit of the k-th physical bit (ascending)
+    int nruns, cnt;
+};
+
+__device__ __forceinline__ uint64_t deposit_runs(uint64_t p, const PhysMarg &q)
+{
+    uint64_t r = 0;
+    for (int k = 0; k < q.nruns; ++k) r |= ((p >> q.src[k]) & ((1ull << q.len[k]) - 1ull)) << q.dst[k];
+    return r;
+}
+
 template <typename C>
-__global__ void __launch_bounds__(256) marg_argmax_stage1(const C *__restrict__ S, BitList qb, BitList ob,
+__global__ void __launch_bounds__(256) marg_argmax_stage1(const C *__restrict__ S, PhysMarg qm, BitList ob,
                                                           double *pv, uint64_t *pi)
 {
-    const uint64_t M = 1ull << qb.cnt, O = 1ull << ob.cnt;
+    const uint64_t M = 1ull << qm.cnt, O = 1ull << ob.cnt;
     double bv = -1.0;
     uint64_t bi = ~0ull;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += stride) {
-        const uint64_t bm = deposit(m, qb);
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += stride) {
+        const uint64_t bm = deposit_runs(p, qm);
         double s = 0.0;
         for (uint64_t o = 0; o < O; ++o) s += prob(S[bm | deposit(o, ob)]);
-        if (better(s, m, bv, bi)) { bv = s; bi = m; }
+        if (s >= bv) {
+            uint64_t m = 0;
+            for (int k = 0; k < qm.cnt; ++k) m |= ((p >> k) & 1ull) << qm.lbit[k];
+            if (better(s, m, bv, bi)) { bv = s; bi = m; }
+        }
     }
     block_argmax(bv, bi, nullptr, nullptr, &pv[blockIdx.x], &pi[blockIdx.x]);
 }
@@ -610,12 +632,36 @@ __global__ void __launch_bounds__(256) marg_argmax_stage1(const C *__restrict__ 
 hipError_t marginal_argmax(const void *S, int n, int dtype, const int *qbits, int nq, const int *obits,
                            void *scratch, uint64_t *res_idx, double *res_val, hipStream_t st)
 {
-    const BitList qb = make_bits(qbits, nq), ob = make_bits(obits, n - nq);
+    const BitList ob = make_bits(obits, n - nq);
+    PhysMarg qm{};
+    qm.cnt = nq;
+    {
+        int order[64];
+        for (int j = 0; j < nq; ++j) order[j] = j;
+        for (int a = 1; a < nq; ++a)  // ascending physical bit
+            for (int b = a; b > 0 && qbits[order[b]] < qbits[order[b - 1]]; --b) {
+                const int t = order[b];
+                order[b] = order[b - 1];
+                order[b - 1] = t;
+            }
+        for (int k = 0; k < nq; ++k) {
+            qm.lbit[k] = (int8_t)order[k];
+            const int phys = qbits[order[k]];
+            if (qm.nruns > 0 && qm.dst[qm.nruns - 1] + qm.len[qm.nruns - 1] == phys) {
+                qm.len[qm.nruns - 1] += 1;
+            } else {
+                qm.src[qm.nruns] = (int8_t)k;
+                qm.dst[qm.nruns] = (int8_t)phys;
+                qm.len[qm.nruns] = 1;
+                qm.nruns += 1;
+            }
+        }
+    }
     double *pv = (double *)scratch;
     uint64_t *pi = (uint64_t *)(pv + AM_BLOCKS);
     const unsigned g = grid_for(1ull << nq, 256, AM_BLOCKS);
-    if (dtype == 0) marg_argmax_stage1<float2><<<g, 256, 0, st>>>((const float2 *)S, qb, ob, pv, pi);
-    else marg_argmax_stage1<double2><<<g, 256, 0, st>>>((const double2 *)S, qb, ob, pv, pi);
+    if (dtype == 0) marg_argmax_stage1<float2><<<g, 256, 0, st>>>((const float2 *)S, qm, ob, pv, pi);
+    else marg_argmax_stage1<double2><<<g, 256, 0, st>>>((const double2 *)S, qm, ob, pv, pi);
     argmax_stage2<<<1, 256, 0, st>>>(pv, pi, (int)g, res_idx, res_val);
     return hipGetLastError();
 }
