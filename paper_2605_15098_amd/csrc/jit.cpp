@@ -147,7 +147,7 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
     o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") svk2_pass_" << idx << "(CT<" << T
       << ">::type *__restrict__ S, svp::K2Args args) {\n"
       << "  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[" << (lds > 0 ? lds : 16) << "];\n"
-      << "  k2_body<" << T << ", " << r << ", " << (vec2 ? "true" : "false") << ">(S, args, lds_raw, Prog" << idx
+      << "  k2_body<" << T << ", " << r << ", " << (vec2 ? "true" : "false") << ", true>(S, args, lds_raw, Prog" << idx
       << "{}, blockIdx.x, gridDim.x);\n}\n";
     return o.str();
 }

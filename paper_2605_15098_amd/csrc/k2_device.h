@@ -514,7 +514,11 @@ __device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t
 // V2 must equal args.vec2: a compile-time access width keeps one load path in
 // the loop, so the wait for the current block counts only its own loads and
 // the next block's prefetch stays in flight.
-template <typename T, int LOGR, bool V2, class Prog>
+//
+// ALWAYS_PREFETCH issues the next block's loads on every iteration (the last
+// re-reads the current block) so their count is the same on every path; a
+// work-group with few blocks (the batched passes) skips it instead.
+template <typename T, int LOGR, bool V2, bool ALWAYS_PREFETCH, class Prog>
 __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
                                         unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
 {
@@ -565,11 +569,10 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     for (;;) {
         const uint64_t next = bid + stride;
         const bool has_next = next < nblocks;
-        // The prefetch is issued on every iteration (the last one re-reads
-        // the current block): with a path-independent count of loads in
-        // flight, the wait for this block's data does not also wait for it.
+        // With a path-independent count of loads in flight, the wait for
+        // this block's data does not also wait for the prefetch.
         const uint64_t nbase = has_next ? uniform64(k2_deposit(next, gmask)) : base;
-        k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
+        if (ALWAYS_PREFETCH || has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
 
         // Block-uniform phase factors of the diagonal runs: each is
         // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in
@@ -612,8 +615,8 @@ template <typename T, int LOGR, class Prog>
 __device__ __forceinline__ void k2_body_any(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
                                             unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
 {
-    if (args.vec2) k2_body<T, LOGR, true>(S, args, lds, prog, first, stride);
-    else k2_body<T, LOGR, false>(S, args, lds, prog, first, stride);
+    if (args.vec2) k2_body<T, LOGR, true, false>(S, args, lds, prog, first, stride);
+    else k2_body<T, LOGR, false, false>(S, args, lds, prog, first, stride);
 }
 
 // ------------------------------------------------------------ interpreter
