@@ -329,7 +329,11 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
             for (int p = 0; p < h->n; ++p)
                 if (!in[p]) a.nbits[k++] = (int8_t)p;
             if (jit[si]) e = svj::launch(jit[si], h->buf, a, h->stream);
-            else e = svk::k2_pass(h->buf, h->n, h->dtype, s.logr, a, h->dops + s.op_begin, h->stream);
+            else {
+                bool mf = false;
+                for (int i = 0; i < s.op_count && !mf; ++i) mf = plan.ops[s.op_begin + i].kind == svp::K2_MFMA;
+                e = svk::k2_pass(h->buf, h->n, h->dtype, s.logr, a, h->dops + s.op_begin, mf, h->stream);
+            }
         }
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         if (h->kernel_timing) {
@@ -1243,7 +1247,9 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     // resident capacity and work-group groups
     const unsigned threads = 1u << (l - logr);
     const size_t lds = std::max<size_t>(max_lds, svp::k2_lds_layout(l, (int)amp, 0, 0, 0).total);
-    const int per_cu = svk::k6_occupancy(dtype, logr, threads, lds);
+    bool mfma = false;
+    for (const svp::K2Op &op : ops) mfma = mfma || op.kind == svp::K2_MFMA;
+    const int per_cu = svk::k6_occupancy(dtype, logr, threads, lds, mfma);
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1) {
@@ -1333,7 +1339,7 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
                                       reinterpret_cast<const int32_t *>(d + o_wg),
                                       reinterpret_cast<const svp::BatchPass *>(d + o_pass),
                                       reinterpret_cast<const svp::K2Op *>(d + o_ops), e->ctrs,
-                                      reinterpret_cast<int *>(e->ctrs + count), 1u << 24, cap_st);
+                                      reinterpret_cast<int *>(e->ctrs + count), 1u << 24, mfma, cap_st);
         he = hipStreamEndCapture(cap_st, &e->graph);
         if (he == hipSuccess) he = h1 != hipSuccess ? h1 : h2;
     }

@@ -621,7 +621,10 @@ __device__ __forceinline__ void k2_body_any(typename CT<T>::type *__restrict__ S
 
 // ------------------------------------------------------------ interpreter
 
-// Runs the op list of a pass (ops[0..nops)) on one block.
+// Runs the op list of a pass (ops[0..nops)) on one block. MFMA selects the
+// build that also runs matrix-core windows: their registers would otherwise
+// weigh on every program the interpreter runs.
+template <bool MFMA>
 struct K2Interp {
     const svp::K2Op *__restrict__ ops;
     int nops;
@@ -658,11 +661,13 @@ struct K2Interp {
 #pragma unroll
                 for (int j = 0; j < LOGR; ++j) rb[j] = nrb[j];
             } else if (kind == svp::K2_MFMA) {
-                int wb[5];
+                if constexpr (MFMA) {
+                    int wb[5];
 #pragma unroll
-                for (int i = 0; i < 5; ++i) wb[i] = (op.c >> (5 * i)) & 31;
-                if (op.b == 4) k2_mfma<LOGR, 4>(a, cx, rb, wb, l, cx.table + op.a);
-                else k2_mfma<LOGR, 5>(a, cx, rb, wb, l, cx.table + op.a);
+                    for (int i = 0; i < 5; ++i) wb[i] = (op.c >> (5 * i)) & 31;
+                    if (op.b == 4) k2_mfma<LOGR, 4>(a, cx, rb, wb, l, cx.table + op.a);
+                    else k2_mfma<LOGR, 5>(a, cx, rb, wb, l, cx.table + op.a);
+                }
             } else if (kind == svp::K2_SCALE) {
                 k2_scale<R>(a, op.v[0]);
             } else if (kind == svp::K2_PHASE) {

@@ -189,12 +189,12 @@ hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st)
 
 // Interpreted block pass: the op list of the pass runs on every block (see
 // k2_body and K2Interp in k2_device.h).
-template <typename T, int LOGR>
+template <typename T, int LOGR, bool MFMA>
 __global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
 k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, svp::K2Args args)
 {
     extern __shared__ unsigned char lds_raw[];
-    k2_body_any<T, LOGR>(S, args, lds_raw, K2Interp{ops, args.nops, args.l}, blockIdx.x, gridDim.x);
+    k2_body_any<T, LOGR>(S, args, lds_raw, K2Interp<MFMA>{ops, args.nops, args.l}, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- k6
@@ -230,7 +230,7 @@ __device__ bool group_barrier(unsigned *ctr, unsigned target, int *err, unsigned
 // Many states in one persistent launch: each work-group serves one instance
 // (wg_inst), runs every pass of that instance's program on its share of the
 // blocks, and waits for the instance's other work-groups between passes.
-template <typename T, int LOGR>
+template <typename T, int LOGR, bool MFMA>
 __global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
 k6_batch_kernel(const svp::BatchInst *__restrict__ insts, const int32_t *__restrict__ wg_inst,
                 const svp::BatchPass *__restrict__ passes, const svp::K2Op *__restrict__ ops, unsigned *ctrs,
@@ -243,7 +243,7 @@ k6_batch_kernel(const svp::BatchInst *__restrict__ insts, const int32_t *__restr
     const uint64_t rank = blockIdx.x - I.group_off;
     for (int p = 0; p < I.npass; ++p) {
         const svp::BatchPass &P = passes[I.pass_off + p];
-        k2_body_any<T, LOGR>((C *)I.S, P.args, lds_raw, K2Interp{ops + P.op_begin, P.args.nops, P.args.l}, rank,
+        k2_body_any<T, LOGR>((C *)I.S, P.args, lds_raw, K2Interp<MFMA>{ops + P.op_begin, P.args.nops, P.args.l}, rank,
                          (uint64_t)I.group_size);
         if (I.group_size > 1 && p + 1 < I.npass)
             if (!group_barrier(&ctrs[I.ctr], (unsigned)((p + 1) * I.group_size), err, limit, &ok)) return;
@@ -262,18 +262,20 @@ hipError_t zero_u32(unsigned *p, uint32_t n, hipStream_t st)
 }
 
 template <typename T>
-static const void *k6_fn(int logr)
+static const void *k6_fn(int logr, bool mfma)
 {
-    switch (logr) {
-    case 3: return (const void *)k6_batch_kernel<T, 3>;
-    case 4: return (const void *)k6_batch_kernel<T, 4>;
+    switch (logr * 2 + (mfma ? 1 : 0)) {
+    case 6: return (const void *)k6_batch_kernel<T, 3, false>;
+    case 7: return (const void *)k6_batch_kernel<T, 3, true>;
+    case 8: return (const void *)k6_batch_kernel<T, 4, false>;
+    case 9: return (const void *)k6_batch_kernel<T, 4, true>;
     default: return nullptr;
     }
 }
 
-int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds)
+int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds, bool mfma)
 {
-    const void *fn = dtype == 0 ? k6_fn<float>(logr) : k6_fn<double>(logr);
+    const void *fn = dtype == 0 ? k6_fn<float>(logr, mfma) : k6_fn<double>(logr, mfma);
     if (!fn) return 0;
     if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
@@ -284,34 +286,22 @@ int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds)
 
 hipError_t k6_batch(int dtype, int logr, unsigned grid, unsigned threads, size_t lds, const svp::BatchInst *insts,
                     const int32_t *wg_inst, const svp::BatchPass *passes, const svp::K2Op *ops, unsigned *ctrs,
-                    int *err, unsigned limit, hipStream_t st)
+                    int *err, unsigned limit, bool mfma, hipStream_t st)
 {
-    if (dtype == 0) {
-        if (logr == 3)
-            k6_batch_kernel<float, 3><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
-        else if (logr == 4)
-            k6_batch_kernel<float, 4><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
-        else
-            return hipErrorInvalidValue;
-    } else {
-        if (logr == 3)
-            k6_batch_kernel<double, 3><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
-        else if (logr == 4)
-            k6_batch_kernel<double, 4><<<grid, threads, lds, st>>>(insts, wg_inst, passes, ops, ctrs, err, limit);
-        else
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const void *fn = dtype == 0 ? k6_fn<float>(logr, mfma) : k6_fn<double>(logr, mfma);
+    if (!fn) return hipErrorInvalidValue;
+    void *args[] = {&insts, &wg_inst, &passes, &ops, &ctrs, &err, &limit};
+    return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, st);
 }
 
-template <typename T, int LOGR>
+template <typename T, int LOGR, bool MFMA>
 static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hipStream_t st)
 {
     using C = typename CT<T>::type;
     const size_t lds = svp::k2_lds_layout(a.l, (int)sizeof(C), a.nug, a.tab_count, a.nut).total;
     static size_t attr_bytes = 64 * 1024;
     if (lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)k2_kernel<T, LOGR>,
+        hipError_t e = hipFuncSetAttribute((const void *)k2_kernel<T, LOGR, MFMA>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_bytes = lds;
@@ -328,35 +318,38 @@ static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hi
         if (e != hipSuccess) return e;
     }
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k2_kernel<T, LOGR>,
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k2_kernel<T, LOGR, MFMA>,
                                                                 (int)threads, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     uint64_t grid = (uint64_t)per_cu * (uint64_t)cus;
     if (grid > blocks) grid = blocks;
-    k2_kernel<T, LOGR><<<(unsigned)grid, threads, lds, st>>>((C *)S, ops, a);
+    k2_kernel<T, LOGR, MFMA><<<(unsigned)grid, threads, lds, st>>>((C *)S, ops, a);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool MFMA>
 static hipError_t k2_dispatch(void *S, int logr, const K2Args &a, const svp::K2Op *ops, hipStream_t st)
 {
     switch (logr) {
-    case 1: return k2_launch_t<T, 1>(S, a, ops, st);
-    case 2: return k2_launch_t<T, 2>(S, a, ops, st);
-    case 3: return k2_launch_t<T, 3>(S, a, ops, st);
-    case 4: return k2_launch_t<T, 4>(S, a, ops, st);
-    case 5: return k2_launch_t<T, 5>(S, a, ops, st);
+    case 1: return k2_launch_t<T, 1, MFMA>(S, a, ops, st);
+    case 2: return k2_launch_t<T, 2, MFMA>(S, a, ops, st);
+    case 3: return k2_launch_t<T, 3, MFMA>(S, a, ops, st);
+    case 4: return k2_launch_t<T, 4, MFMA>(S, a, ops, st);
+    case 5: return k2_launch_t<T, 5, MFMA>(S, a, ops, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *ops,
+hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *ops, bool mfma,
                    hipStream_t st)
 {
     if (a.l < logr || a.l > n || logr < 1) return hipErrorInvalidValue;
-    return dtype == 0 ? k2_dispatch<float>(S, logr, a, ops, st)
-                      : k2_dispatch<double>(S, logr, a, ops, st);
+    if (mfma)
+        return dtype == 0 ? k2_dispatch<float, true>(S, logr, a, ops, st)
+                          : k2_dispatch<double, true>(S, logr, a, ops, st);
+    return dtype == 0 ? k2_dispatch<float, false>(S, logr, a, ops, st)
+                      : k2_dispatch<double, false>(S, logr, a, ops, st);
 }
 
 // ---------------------------------------------------------------- k5 readouts

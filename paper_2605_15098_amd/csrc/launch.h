@@ -18,14 +18,16 @@ hipError_t init_zero_state(void *S, int n, int dtype, hipStream_t st);
 // Batched passes: see k6_batch_kernel. grid must not exceed the resident
 // capacity (k6_occupancy work-groups per CU times the CU count) so that the
 // work-groups of one instance can wait for each other.
-int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds);
+// mfma: some pass runs matrix-core windows (selects that build of the kernel).
+int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds, bool mfma);
 hipError_t k6_batch(int dtype, int logr, unsigned grid, unsigned threads, size_t lds, const svp::BatchInst *insts,
                     const int32_t *wg_inst, const svp::BatchPass *passes, const svp::K2Op *ops, unsigned *ctrs,
-                    int *err, unsigned limit, hipStream_t st);
+                    int *err, unsigned limit, bool mfma, hipStream_t st);
 hipError_t zero_u32(unsigned *p, uint32_t n, hipStream_t st);
 hipError_t k1_gate(void *S, int n, int dtype, const svp::MGate &g, hipStream_t st);
 hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st);
-hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *dev_ops,
+// mfma: the op list holds matrix-core windows.
+hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *dev_ops, bool mfma,
                    hipStream_t st);
 
 // Readouts (FP64). perm: HOST array of n ints, perm[q] = physical bit of
