@@ -779,17 +779,18 @@ std::vector<sv_schedule> candidates(int n, int dtype)
     for (int l = std::max(1, top - 2); l <= top; ++l)
         for (int r = r0; r <= r0 + 1; ++r) {
             if (r > l && r != r0) continue;  // small blocks: one tile of 2^l
-            for (int pol : {SV_SWAP_LOOKAHEAD, SV_SWAP_LRU}) {
-                sv_schedule c{};
-                c.mode = SV_PARTITIONED;
-                c.block_qubits = l;
-                c.fuse_k = 1;
-                c.swap_policy = pol;
-                c.remap = SV_REMAP_VIRTUAL;
-                c.diag_free = 1;
-                c.reg_qubits = std::min(r, l);
-                out.push_back(c);
-            }
+            for (int pol : {SV_SWAP_LOOKAHEAD, SV_SWAP_LRU})
+                for (int fk : {1, 5}) {
+                    sv_schedule c{};
+                    c.mode = SV_PARTITIONED;
+                    c.block_qubits = l;
+                    c.fuse_k = fk;
+                    c.swap_policy = pol;
+                    c.remap = SV_REMAP_VIRTUAL;
+                    c.diag_free = 1;
+                    c.reg_qubits = std::min(r, l);
+                    out.push_back(c);
+                }
         }
     return out;
 }
