@@ -220,7 +220,9 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
         return fail(SV_ERR_UNSUPPORTED, "dense fusion windows have 4 or 5 qubits");
     if (s->fuse_k >= 4 && s->mode != SV_PARTITIONED)
         return fail(SV_ERR_UNSUPPORTED, "dense fusion runs inside block passes (partitioned mode)");
-    if (s->outer_qubits != 0) return fail(SV_ERR_UNSUPPORTED, "outer tier is not available in this build");
+    if (s->outer_qubits < 0 || s->outer_qubits > 40) return fail(SV_ERR_INVALID_ARG, "outer_qubits out of range");
+    if (s->outer_qubits > 0 && s->mode != SV_PARTITIONED)
+        return fail(SV_ERR_UNSUPPORTED, "the outer tier chains block passes (partitioned mode)");
     if (s->tuner != SV_TUNER_NONE && s->tuner != SV_TUNER_EXHAUSTIVE && s->tuner != SV_TUNER_LEARNED)
         return fail(SV_ERR_INVALID_ARG, "unknown tuner");
     if (s->reg_qubits < 0) return fail(SV_ERR_INVALID_ARG, "reg_qubits < 0");
@@ -229,7 +231,11 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
     return SV_OK;
 }
 
-sv_status run_plan(sv_handle h, const svp::Plan &plan)
+// Bytes of outer blocks one chained launch covers (half of the 256 MB
+// Infinity Cache).
+constexpr double kOuterChunkBytes = 128.0 * 1024 * 1024;
+
+sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
 {
     const auto tu0 = std::chrono::steady_clock::now();
     if (!plan.ops.empty()) {
@@ -287,59 +293,111 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan)
     }
     const auto tp1 = std::chrono::steady_clock::now();
     h->kev_kind.clear();
-    if (h->kernel_timing) {
-        const size_t need = 2 * plan.steps.size();
-        while (h->kev.size() < need) {
-            hipEvent_t e;
-            SV_HIP(hipEventCreate(&e), "hipEventCreate");
-            h->kev.push_back(e);
-        }
-    }
-    SV_HIP(hipEventRecord(h->ev0, h->stream), "hipEventRecord");
-    for (size_t si = 0; si < plan.steps.size(); ++si) {
+    // One launch of block pass si over 2^nblk blocks: the bits of the block
+    // number are `vary` (ascending), every block also carries base_or.
+    auto launch_k2 = [&](size_t si, const std::vector<int> &vary, uint64_t base_or) -> hipError_t {
         const svp::Step &s = plan.steps[si];
-        if (launch_fault()) return fail(SV_ERR_DEVICE, "injected launch failure");
-        hipError_t e = hipSuccess;
+        svk::K2Args a{};
+        a.n = h->n;
+        a.l = s.l;
+        a.nops = s.op_count;
+        a.nug = s.nug;
+        a.ug_off = s.ug_off;
+        a.tab_off = s.tab_off;
+        a.tab_count = s.tab_count;
+        a.ut_off = s.ut_off;
+        a.nut = s.nut;
+        a.table = h->dtab;
+        a.vec2 = (s.l >= 2 && s.logr >= 2 && s.bits[0] == 0) ? 1 : 0;
+        for (int i = 0; i < s.l; ++i) a.bits[i] = (int8_t)s.bits[i];
+        for (size_t k = 0; k < vary.size(); ++k) a.nbits[k] = (int8_t)vary[k];
+        a.nblk_bits = (int32_t)vary.size();
+        a.base_or = base_or;
+        if (jit[si]) return svj::launch(jit[si], h->buf, a, h->stream);
+        bool mf = false;
+        for (int i = 0; i < s.op_count && !mf; ++i) mf = plan.ops[s.op_begin + i].kind == svp::K2_MFMA;
+        return svk::k2_pass(h->buf, h->n, h->dtype, s.logr, a, h->dops + s.op_begin, mf, h->stream);
+    };
+    auto local_mask = [&](const svp::Step &s) {
+        uint64_t m = 0;
+        for (int i = 0; i < s.l; ++i) m |= 1ull << s.bits[i];
+        return m;
+    };
+    auto timed = [&](int kind, auto &&fn) -> sv_status {
         if (h->kernel_timing) {
+            while (h->kev.size() < 2 * h->kev_kind.size() + 2) {
+                hipEvent_t ev;
+                SV_HIP(hipEventCreate(&ev), "hipEventCreate");
+                h->kev.push_back(ev);
+            }
             SV_HIP(hipEventRecord(h->kev[2 * h->kev_kind.size()], h->stream), "hipEventRecord");
         }
-        if (s.kind == svp::ST_K1) {
-            e = svk::k1_gate(h->buf, h->n, h->dtype, s.g, h->stream);
-        } else if (s.kind == svp::ST_K3) {
-            e = svk::k3_swap(h->buf, h->n, h->dtype, s.p, s.v, h->stream);
-        } else {
-            svk::K2Args a{};
-            a.n = h->n;
-            a.l = s.l;
-            a.nops = s.op_count;
-            a.nug = s.nug;
-            a.ug_off = s.ug_off;
-            a.tab_off = s.tab_off;
-            a.tab_count = s.tab_count;
-            a.ut_off = s.ut_off;
-            a.nut = s.nut;
-            a.table = h->dtab;
-            a.vec2 = (s.l >= 2 && s.logr >= 2 && s.bits[0] == 0) ? 1 : 0;
-            std::vector<bool> in(h->n, false);
-            for (int i = 0; i < s.l; ++i) {
-                a.bits[i] = (int8_t)s.bits[i];
-                in[s.bits[i]] = true;
-            }
-            int k = 0;
-            for (int p = 0; p < h->n; ++p)
-                if (!in[p]) a.nbits[k++] = (int8_t)p;
-            if (jit[si]) e = svj::launch(jit[si], h->buf, a, h->stream);
-            else {
-                bool mf = false;
-                for (int i = 0; i < s.op_count && !mf; ++i) mf = plan.ops[s.op_begin + i].kind == svp::K2_MFMA;
-                e = svk::k2_pass(h->buf, h->n, h->dtype, s.logr, a, h->dops + s.op_begin, mf, h->stream);
-            }
-        }
+        if (launch_fault()) return fail(SV_ERR_DEVICE, "injected launch failure");
+        hipError_t e = fn();
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         if (h->kernel_timing) {
             SV_HIP(hipEventRecord(h->kev[2 * h->kev_kind.size() + 1], h->stream), "hipEventRecord");
-            h->kev_kind.push_back(s.kind == svp::ST_K1 ? 0 : (s.kind == svp::ST_K2 ? 1 : 2));
+            h->kev_kind.push_back(kind);
         }
+        return SV_OK;
+    };
+    SV_HIP(hipEventRecord(h->ev0, h->stream), "hipEventRecord");
+    for (size_t si = 0; si < plan.steps.size();) {
+        const svp::Step &s = plan.steps[si];
+        if (s.kind == svp::ST_K1) {
+            if (sv_status st = timed(0, [&] { return svk::k1_gate(h->buf, h->n, h->dtype, s.g, h->stream); })) return st;
+            ++si;
+            continue;
+        }
+        if (s.kind == svp::ST_K3) {
+            if (sv_status st = timed(2, [&] { return svk::k3_swap(h->buf, h->n, h->dtype, s.p, s.v, h->stream); }))
+                return st;
+            ++si;
+            continue;
+        }
+        // Outer tier: consecutive block passes whose local bits together fit
+        // in outer_qubits bits run chunk by chunk, every pass of the chain on
+        // one chunk of outer blocks before the next chunk, so the later
+        // passes find the chunk in the Infinity Cache.
+        uint64_t U = local_mask(s);
+        size_t sj = si + 1;
+        if (outer_qubits > 0)
+            while (sj < plan.steps.size() && plan.steps[sj].kind == svp::ST_K2 &&
+                   __builtin_popcountll(U | local_mask(plan.steps[sj])) <= outer_qubits) {
+                U |= local_mask(plan.steps[sj]);
+                ++sj;
+            }
+        if (sj - si < 2) {
+            std::vector<int> vary;
+            for (int p = 0; p < h->n; ++p)
+                if (!((local_mask(s) >> p) & 1ull)) vary.push_back(p);
+            if (sv_status st = timed(1, [&] { return launch_k2(si, vary, 0); })) return st;
+            ++si;
+            continue;
+        }
+        const int u = __builtin_popcountll(U);
+        std::vector<int> rest;  // memory bits outside the outer block, ascending
+        for (int p = 0; p < h->n; ++p)
+            if (!((U >> p) & 1ull)) rest.push_back(p);
+        const double outer_bytes = std::ldexp((double)amp_bytes(h->dtype), u);
+        int c = 0;  // chunk bits: 2^c outer blocks per launch, within the cache budget
+        while (c < (int)rest.size() && std::ldexp(outer_bytes, c + 1) <= kOuterChunkBytes) ++c;
+        const std::vector<int> chunk(rest.begin(), rest.begin() + c), high(rest.begin() + c, rest.end());
+        const uint64_t nchunks = 1ull << high.size();
+        for (uint64_t j = 0; j < nchunks; ++j) {
+            uint64_t base_or = 0;
+            for (size_t k = 0; k < high.size(); ++k)
+                if ((j >> k) & 1ull) base_or |= 1ull << high[k];
+            for (size_t sk = si; sk < sj; ++sk) {
+                const uint64_t lm = local_mask(plan.steps[sk]);
+                std::vector<int> vary;
+                for (int p = 0; p < h->n; ++p)
+                    if (((U >> p) & 1ull) && !((lm >> p) & 1ull)) vary.push_back(p);
+                vary.insert(vary.end(), chunk.begin(), chunk.end());
+                if (sv_status st = timed(1, [&] { return launch_k2(sk, vary, base_or); })) return st;
+            }
+        }
+        si = sj;
     }
     SV_HIP(hipEventRecord(h->ev1, h->stream), "hipEventRecord");
     h->timed = true;
@@ -513,7 +571,7 @@ sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv
     std::string err = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates), m, h->l2p, plan);
     if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
     const auto t1 = std::chrono::steady_clock::now();
-    if (sv_status st = run_plan(h, plan)) return st;
+    if (sv_status st = run_plan(h, plan, s ? s->outer_qubits : 0)) return st;
     h->l2p = plan.l2p_after;
     std::memset(&h->st, 0, sizeof(h->st));
     fill_stats(&h->st, c, plan);
@@ -1239,6 +1297,8 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
             int k = 0;
             for (int p = 0; p < hs[i]->n; ++p)
                 if (!in[p]) bp.args.nbits[k++] = (int8_t)p;
+            bp.args.nblk_bits = hs[i]->n - st.l;
+            bp.args.base_or = 0;
             bp.op_begin = ob + st.op_begin;
             passes.push_back(bp);
             insts[i].npass += 1;

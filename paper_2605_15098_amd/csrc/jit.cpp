@@ -323,7 +323,7 @@ hipError_t prepare_plan(const svp::Plan &plan, int dtype, std::vector<const void
 hipError_t launch(const void *handle, void *S, const svp::K2Args &a, hipStream_t st)
 {
     const Kernel &e = *static_cast<const Kernel *>(handle);
-    const uint64_t blocks = 1ull << (a.n - a.l);
+    const uint64_t blocks = 1ull << a.nblk_bits;
     uint64_t grid = (uint64_t)e.per_cu * (uint64_t)g_cus;
     if (grid > blocks) grid = blocks;
     svp::K2Args args = a;

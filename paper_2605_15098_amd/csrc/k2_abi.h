@@ -97,6 +97,13 @@ struct K2Args {
     int32_t tab_count;         // table (tab_count complex doubles), staged in LDS
     int32_t ut_off;            // byte offset of the pass's UTerm array
     int32_t nut;               // its length (staged in LDS with the UGroups)
+    // Blocks of this launch: block number b (0 <= b < 2^nblk_bits) is
+    // deposited into memory bits nbits[0..nblk_bits) and OR-ed with base_or.
+    // A whole-state pass has nblk_bits = n - l and base_or = 0; the outer
+    // tier launches a pass on one chunk of outer blocks at a time.
+    uint64_t base_or;
+    int32_t nblk_bits;
+    int32_t pad_;
 };
 
 // LDS of a block pass, in this order (16-byte aligned pieces): the block

@@ -527,7 +527,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     const int l = args.l;
     const int tb = l - LOGR;
     const uint32_t tid = threadIdx.x;
-    const uint64_t nblocks = 1ull << (args.n - l);
+    const uint64_t nblocks = 1ull << args.nblk_bits;
     constexpr bool vec2 = V2;
     const svp::K2Lds L = svp::k2_lds_layout(l, (int)sizeof(C), args.nug, args.tab_count, args.nut);
     double2 *ufac = reinterpret_cast<double2 *>(lds + L.ufac);
@@ -536,8 +536,9 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     svp::UGroup *ugrp = reinterpret_cast<svp::UGroup *>(lds + L.ugrp);
     // memory bits outside the block, as a mask (the block number is deposited there)
     uint64_t gmask = 0;
-    for (int i = 0; i < args.n - l; ++i) gmask |= 1ull << args.nbits[i];
+    for (int i = 0; i < args.nblk_bits; ++i) gmask |= 1ull << args.nbits[i];
     gmask = uniform64(gmask);
+    const uint64_t base_or = uniform64(args.base_or);
 
     // canonical-layout addressing, the same for every block
     uint64_t tmem_local = 0;
@@ -562,7 +563,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         for (int i = (int)tid; i < args.nug; i += (int)blockDim.x) ugrp[i] = gs[i];
         __syncthreads();
     }
-    uint64_t base = uniform64(k2_deposit(bid, gmask));
+    uint64_t base = uniform64(k2_deposit(bid, gmask) | base_or);
     C a[R], b[R];
     k2_load<LOGR>(a, S, base | tmem_local, roff, vec2);
 
@@ -571,7 +572,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         const bool has_next = next < nblocks;
         // With a path-independent count of loads in flight, the wait for
         // this block's data does not also wait for the prefetch.
-        const uint64_t nbase = has_next ? uniform64(k2_deposit(next, gmask)) : base;
+        const uint64_t nbase = has_next ? uniform64(k2_deposit(next, gmask) | base_or) : base;
         if (ALWAYS_PREFETCH || has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
 
         // Block-uniform phase factors of the diagonal runs: each is

@@ -307,7 +307,7 @@ static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hi
         attr_bytes = lds;
     }
     const unsigned threads = 1u << (a.l - LOGR);
-    const uint64_t blocks = 1ull << (a.n - a.l);
+    const uint64_t blocks = 1ull << a.nblk_bits;
     if (threads > (unsigned)k2_max_threads<T, LOGR>()) return hipErrorInvalidConfiguration;
     // persistent grid: as many work-groups as fit on the device at once
     static int cus = 0;

@@ -68,6 +68,12 @@ def test_schedule_errors():
     with pytest.raises(sv.SvError) as e:
         sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=-1))
     assert e.value.status == sv.SV_ERR_INVALID_ARG
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(6, "c64", g, sv.schedule("plain", outer_qubits=5))
+    assert e.value.status == sv.SV_ERR_UNSUPPORTED
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(6, "c64", g, sv.schedule(outer_qubits=-2))
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
     # matrix-core windows need blocks of whole waves (2^(l - 4) >= 64 threads)
     assert sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=5))["fused"] == 0
     assert sv.sv_plan(12, "c64", W.qpe_gates(12, 0.25), sv.schedule(fuse_k=5))["fused"] > 0
