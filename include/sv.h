@@ -97,13 +97,15 @@ typedef struct {
     int32_t block_qubits; /* l, local qubits per on-chip block; 0 = default   */
     int32_t outer_qubits; /* l2 (0 = off): outer tier. Consecutive block
                              passes whose local qubits together number at
-                             most l2 run chunk by chunk (128 MiB of outer
-                             blocks per launch, every pass of the chain on a
-                             chunk before the next chunk), so the later
-                             passes of a chain read the chunk from the
-                             Infinity Cache (Section III-B's cache-resident
-                             block, one tier up). Results are bit-identical
-                             to l2 = 0. Partitioned mode only; 0..40.       */
+                             most l2 run outer block by outer block (2^l2
+                             amplitudes: the chain's local qubits plus the
+                             lowest other qubits; one launch per pass and
+                             outer block), so the later passes of a chain
+                             read the block from the Infinity Cache
+                             (Section III-B's cache-resident block, one tier
+                             up; 2^24 complex64 = 128 MiB of the 256 MB).
+                             Results are bit-identical to l2 = 0.
+                             Partitioned mode only; 0..40.                   */
     int32_t fuse_k;       /* 0: one device op per gate (bit-exact with the
                              plain path); 1: each run of diagonal gates in a
                              block pass becomes one phase multiply per

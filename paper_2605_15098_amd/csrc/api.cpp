@@ -231,10 +231,6 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
     return SV_OK;
 }
 
-// Bytes of outer blocks one chained launch covers (half of the 256 MB
-// Infinity Cache).
-constexpr double kOuterChunkBytes = 128.0 * 1024 * 1024;
-
 sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
 {
     const auto tu0 = std::chrono::steady_clock::now();
@@ -356,9 +352,9 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
             continue;
         }
         // Outer tier: consecutive block passes whose local bits together fit
-        // in outer_qubits bits run chunk by chunk, every pass of the chain on
-        // one chunk of outer blocks before the next chunk, so the later
-        // passes find the chunk in the Infinity Cache.
+        // in outer_qubits bits run outer block by outer block (2^outer_qubits
+        // amplitudes), every pass of the chain on one outer block before the
+        // next, so the later passes find the block in the Infinity Cache.
         uint64_t U = local_mask(s);
         size_t sj = si + 1;
         if (outer_qubits > 0)
@@ -379,9 +375,9 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
         std::vector<int> rest;  // memory bits outside the outer block, ascending
         for (int p = 0; p < h->n; ++p)
             if (!((U >> p) & 1ull)) rest.push_back(p);
-        const double outer_bytes = std::ldexp((double)amp_bytes(h->dtype), u);
-        int c = 0;  // chunk bits: 2^c outer blocks per launch, within the cache budget
-        while (c < (int)rest.size() && std::ldexp(outer_bytes, c + 1) <= kOuterChunkBytes) ++c;
+        // an outer block is 2^outer_qubits amplitudes: the chain's local bits
+        // and the lowest c remaining bits; one launch per pass and outer block
+        const int c = std::min((int)rest.size(), outer_qubits - u);
         const std::vector<int> chunk(rest.begin(), rest.begin() + c), high(rest.begin() + c, rest.end());
         const uint64_t nchunks = 1ull << high.size();
         for (uint64_t j = 0; j < nchunks; ++j) {

@@ -32,7 +32,7 @@ def run(n, dtype, g, sched):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("n,l,l2", [(14, 8, 11), (16, 9, 14), (18, 10, 16)])
+@pytest.mark.parametrize("n,l,l2", [(14, 8, 11), (16, 9, 13), (18, 10, 16)])
 def test_outer_tier_bitwise_equal_small(n, l, l2, dtype):
     rng = np.random.default_rng(n + l2)
     g = W.random_mixed_circuit(n, 120, rng)
@@ -46,13 +46,14 @@ def test_outer_tier_bitwise_equal_small(n, l, l2, dtype):
 
 
 def test_outer_tier_chunks_qpe_26():
-    """A 512 MiB complex64 state: chains of passes split into several 128 MiB
-    chunks of outer blocks (more launches than passes)."""
+    """A 512 MiB complex64 state with outer blocks of 2^20 amplitudes: each
+    chained pass runs as one launch per outer block (more launches than
+    passes)."""
     n, phi = 26, 0.3183
     g = W.qpe_gates(n, phi)
     log("case outer qpe26")
     a, sa, _ = run(n, "c64", g, sv.schedule(block_qubits=11))
-    b, sb, _ = run(n, "c64", g, sv.schedule(block_qubits=11, outer_qubits=18))
+    b, sb, _ = run(n, "c64", g, sv.schedule(block_qubits=11, outer_qubits=20))
     assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
     assert sb["kernel_launches"][1] > sb["passes"]
     idx = np.arange(0, 1 << (n - 1), 4099)
