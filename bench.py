@@ -295,6 +295,7 @@ def main():
         for name, dt, sch, st_, wu in (
                 ("c128-plain", "c128", sv.schedule("plain"), 1, 1),
                 ("c128-partitioned", "c128", sv.schedule(), 3, 1),
+                ("c64-partitioned-outer-tier-l2-25", "c64", sv.schedule(outer_qubits=25), 4, 2),
                 ("c64-plain", "c64", sv.schedule("plain"), 1, 1),
                 ("c64-paper-lru-l13", "c64", sv.paper_schedule(13), 1, 1)):
             log(f"comparison {name}")
