@@ -100,8 +100,12 @@ def precompile(jobs: Sequence[tuple], workers: int) -> List[float]:
 
 
 def circuit(kind: str, idx: int):
+    """'train' (20-26 qubits), 'train:lo:hi' (lo..hi qubits) or 'eval'."""
     if kind == "train":
         return W.circuit_random_train(idx)
+    if kind.startswith("train:"):
+        _, lo, hi = kind.split(":")
+        return W.circuit_random_train(idx, lo=int(lo), hi=int(hi))
     if kind == "eval":
         return W.circuit_random_eval(idx)
     raise ValueError(kind)
@@ -113,19 +117,20 @@ def _fields(s) -> tuple:
 
 # ---------------------------------------------------------------- data collection
 
-def collect(idxs: Sequence[int], dtype: str = "c64", repeats: int = 3, workers: int = 12) -> dict:
+def collect(idxs: Sequence[int], dtype: str = "c64", repeats: int = 3, workers: int = 12,
+            kind: str = "train") -> dict:
     jobs = []
     for i in idxs:
-        n, g = circuit("train", i)
+        n, g = circuit(kind, i)
         for c in sv.sv_tune_candidates(n, dtype):
-            jobs.append((n, dtype, "train", i, _fields(c)))
+            jobs.append((n, dtype, kind, i, _fields(c)))
     log(f"{len(idxs)} circuits, {len(jobs)} (circuit, candidate) pairs")
     t0 = time.perf_counter()
     csec = precompile(jobs, workers)
     log(f"compiled in {time.perf_counter() - t0:.1f} s")
     rows, ys, cid, cidx, cms_all = [], [], [], [], []
     for k, i in enumerate(idxs):
-        n, g = circuit("train", i)
+        n, g = circuit(kind, i)
         cands, X = candidate_features(n, dtype, g)
         st = sv.StateVector(n, dtype)
         ms, cms = sv.sv_tune_time(st.h, g, cands, repeats)
@@ -295,10 +300,11 @@ def main(argv=None) -> int:
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
     c.add_argument("--circuits", default="0:120")
+    c.add_argument("--qubits", default="20:26", help="lo:hi qubits of the training circuits")
     c.add_argument("--workers", type=int, default=12)
     c.add_argument("--out", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--data", required=True)
+    t.add_argument("--data", required=True, help="one or more collected .npz files, comma separated")
     t.add_argument("--epochs", type=int, default=400)
     t.add_argument("--out", required=True)
     e = sub.add_parser("eval")
@@ -309,12 +315,19 @@ def main(argv=None) -> int:
     e.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
-        d = collect(_range(a.circuits), workers=a.workers)
+        lo, hi = a.qubits.split(":")
+        kind = "train" if (lo, hi) == ("20", "26") else f"train:{lo}:{hi}"
+        d = collect(_range(a.circuits), workers=a.workers, kind=kind)
         np.savez(a.out, **d)
         log(f"wrote {a.out}")
     elif a.cmd == "train":
-        with np.load(a.data, allow_pickle=False) as z:
-            X, ms, cid = z["X"], z["ms"], z["circuit"]
+        Xs, mss, cids = [], [], []
+        for k, path in enumerate(a.data.split(",")):
+            with np.load(path, allow_pickle=False) as z:
+                Xs.append(z["X"])
+                mss.append(z["ms"])
+                cids.append(z["circuit"] + 100000 * k)
+        X, ms, cid = np.concatenate(Xs), np.concatenate(mss), np.concatenate(cids)
         params, norm, hist = train(X, ms, epochs=a.epochs)
         pred = predict(params, norm, X)
         meta = {"features": sv.FEATURE_NAMES, "samples": int(len(ms)),
