@@ -121,6 +121,12 @@ typedef struct {
                              schedule itself (sv_tune); NONE = use this one   */
     int32_t reg_qubits;   /* amplitudes per thread in a block pass = 2^this;
                              0 = default (4)                                  */
+    int32_t pin_qubits;   /* low physical qubits local in every block with
+                             virtual remap: contiguous runs of 2^this
+                             amplitudes per access; 0 = default (4 for
+                             complex64 = 128-byte segments, 3 for
+                             complex128); more pins leave fewer free local
+                             qubits per pass                                  */
 } sv_schedule;
 
 typedef struct {

@@ -197,6 +197,7 @@ svp::PlanConfig config_from(sv_handle h, const sv_schedule *s)
         c.diag_free = s->diag_free;
         c.fuse_k = s->fuse_k;
         if (s->reg_qubits > 0) c.logr = s->reg_qubits;
+        if (s->pin_qubits > 0) c.pin_low = s->pin_qubits;
     }
     if (const char *e = std::getenv("SV_PIN_BITS")) c.pin_low = std::atoi(e);
     if (const char *e = std::getenv("SV_LOGR")) c.logr = std::atoi(e);
@@ -226,6 +227,7 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
     if (s->tuner != SV_TUNER_NONE && s->tuner != SV_TUNER_EXHAUSTIVE && s->tuner != SV_TUNER_LEARNED)
         return fail(SV_ERR_INVALID_ARG, "unknown tuner");
     if (s->reg_qubits < 0) return fail(SV_ERR_INVALID_ARG, "reg_qubits < 0");
+    if (s->pin_qubits < 0 || s->pin_qubits > 16) return fail(SV_ERR_INVALID_ARG, "pin_qubits out of range");
     if (s->reg_qubits > (dtype == SV_COMPLEX64 ? 5 : 4))
         return fail(SV_ERR_UNSUPPORTED, "reg_qubits above the register budget for this dtype");
     return SV_OK;

@@ -47,7 +47,7 @@ class sv_schedule(ctypes.Structure):
                 ("outer_qubits", ctypes.c_int32), ("fuse_k", ctypes.c_int32),
                 ("swap_policy", ctypes.c_int32), ("remap", ctypes.c_int32),
                 ("diag_free", ctypes.c_int32), ("tuner", ctypes.c_int32),
-                ("reg_qubits", ctypes.c_int32)]
+                ("reg_qubits", ctypes.c_int32), ("pin_qubits", ctypes.c_int32)]
 
 
 class sv_stats(ctypes.Structure):
@@ -61,7 +61,7 @@ class sv_stats(ctypes.Structure):
 
 
 def schedule(mode="partitioned", block_qubits=0, outer_qubits=0, fuse_k=1, swap_policy="lookahead",
-             remap="virtual", diag_free=True, tuner="none", reg_qubits=0) -> sv_schedule:
+             remap="virtual", diag_free=True, tuner="none", reg_qubits=0, pin_qubits=0) -> sv_schedule:
     s = sv_schedule()
     s.mode = {"plain": SV_PLAIN, "partitioned": SV_PARTITIONED}.get(mode, mode)
     s.block_qubits = int(block_qubits)
@@ -73,6 +73,7 @@ def schedule(mode="partitioned", block_qubits=0, outer_qubits=0, fuse_k=1, swap_
     s.tuner = {"none": SV_TUNER_NONE, "exhaustive": SV_TUNER_EXHAUSTIVE,
                "learned": SV_TUNER_LEARNED}.get(tuner, tuner)
     s.reg_qubits = int(reg_qubits)
+    s.pin_qubits = int(pin_qubits)
     return s
 
 
