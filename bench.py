@@ -199,7 +199,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--dtype", default="c64")
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--block", type=int, default=-1, help="block qubits (default: 14 for c64, library default for c128)")
+    ap.add_argument("--pin", type=int, default=-1, help="pinned low qubits (default: 5 for c64)")
+    ap.add_argument("--reg", type=int, default=-1, help="register qubits per thread (default: 5 for c64)")
     ap.add_argument("--quick", action="store_true", help="skip comparison runs and CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -223,7 +225,14 @@ def main():
     gates = W.qpe_gates(n, phi)
     ngates = W.qpe_gate_count(n)[0]
     ab = 8 if args.dtype == "c64" else 16
-    sched = sv.schedule(block_qubits=args.block)
+    # complex64 default: the schedule the tuner sweep found fastest on this
+    # workload (2^14-amplitude blocks, 5 pinned low qubits = 256-byte runs,
+    # 32 amplitudes per thread); complex128 keeps the library defaults
+    c64 = args.dtype == "c64"
+    block = args.block if args.block >= 0 else (14 if c64 else 0)
+    pin = args.pin if args.pin >= 0 else (5 if c64 else 0)
+    reg = args.reg if args.reg >= 0 else (5 if c64 else 0)
+    sched = sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg)
 
     log(f"workload qpe n={n} dtype={args.dtype} phi_seed={seed} gates={ngates}")
     sim = sv.StateVector(n, args.dtype)
@@ -259,6 +268,7 @@ def main():
             "n_qubits": n, "counting_qubits": n - 1, "phi_seed": seed, "phi": phi,
             "gates_per_step": ngates, "swap_relabels": (n - 1) // 2,
             "schedule": {"mode": "partitioned", "block_qubits": st["block_qubits"],
+                         "pin_qubits": pin or "default", "reg_qubits": reg or "default",
                          "swap_policy": "lookahead-bulk", "remap": "virtual", "diag_free": True},
             "passes_per_step": st["passes"], "swaps_per_step": st["swaps"],
         },
@@ -272,7 +282,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": k2_achieved / HBM_PEAK_GBPS,
-            "traffic": measured_traffic("k2", f"qpe{n}-{args.dtype}"),
+            "traffic": measured_traffic("k2", f"qpe{n}-{args.dtype}-l{st['block_qubits']}p{pin}r{reg}"),
             "algorithmic_bytes_per_launch": pass_bytes,
             "launches": kl[1],
             "avg_launch_ms": kms[1] / kl[1] if kl[1] else None,
@@ -295,7 +305,9 @@ def main():
         for name, dt, sch, st_, wu in (
                 ("c128-plain", "c128", sv.schedule("plain"), 1, 1),
                 ("c128-partitioned", "c128", sv.schedule(), 3, 1),
-                ("c64-partitioned-outer-tier-l2-25", "c64", sv.schedule(outer_qubits=25), 4, 2),
+                ("c64-partitioned-l13-defaults", "c64", sv.schedule(block_qubits=13), 4, 2),
+                ("c64-partitioned-outer-tier-l2-25", "c64",
+                 sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, outer_qubits=25), 4, 2),
                 ("c64-plain", "c64", sv.schedule("plain"), 1, 1),
                 ("c64-paper-lru-l13", "c64", sv.paper_schedule(13), 1, 1)):
             log(f"comparison {name}")

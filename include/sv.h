@@ -248,18 +248,20 @@ sv_status sv_plan(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const s
 /* ---- schedule tuning (the paper sweeps the block size by hand over a
  * range and keeps the median of three runs, Section IV-B) ----
  *
- * Candidates: partitioned schedules with virtual remap and diagonal gates
- * free, over
- *   block qubits  the three largest sizes that fit on chip (complex64 11..13,
- *                 complex128 10..12; capped at n),
+ * Candidates: partitioned schedules with look-ahead bulk remap (virtual) and
+ * diagonal gates free, over
+ *   block qubits  the three largest sizes that fit on chip (complex64 12..14,
+ *                 complex128 11..13; capped at n),
  *   register tile 2^4 or 2^5 amplitudes per thread (complex64),
  *                 2^3 or 2^4 (complex128),
- *   swap placement look-ahead bulk remap or LRU,
+ *   pinned low    4 or 5 qubits (complex64), 3 or 4 (complex128),
  *   fusion        fuse_k 1 (diagonal runs combined) or 5 (also dense windows
  *                 of up to 5 qubits through the matrix cores)
- * (a block smaller than the register tile is one tile). sv_tune_candidates
- * writes up to cap of them to out (out may be NULL) and their number to
- * *count (24 when n is at least the largest size). */
+ * (a block smaller than the register tile is one tile). The paper's LRU
+ * placement is left out: it never came within a factor of two of look-ahead
+ * on the measured circuits. sv_tune_candidates writes up to cap of them to
+ * out (out may be NULL) and their number to *count (24 when n is at least
+ * the largest size). */
 sv_status sv_tune_candidates(int n, sv_dtype dtype, sv_schedule *out, int cap, int *count);
 
 /* Pick a schedule for this circuit on this handle among the candidates.

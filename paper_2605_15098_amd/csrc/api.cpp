@@ -830,23 +830,27 @@ CostModel g_model;
 std::vector<sv_schedule> candidates(int n, int dtype)
 {
     std::vector<sv_schedule> out;
-    const int top = std::min(n, svp::default_block_qubits(dtype));
+    const int top = std::min(n, svp::max_block_qubits(dtype));
     const int r0 = dtype == SV_COMPLEX64 ? 4 : 3;
+    const int p0 = dtype == SV_COMPLEX64 ? 4 : 3;  // 128-byte segments
     for (int l = std::max(1, top - 2); l <= top; ++l)
         for (int r = r0; r <= r0 + 1; ++r) {
             if (r > l && r != r0) continue;  // small blocks: one tile of 2^l
-            for (int pol : {SV_SWAP_LOOKAHEAD, SV_SWAP_LRU})
+            for (int p = p0; p <= p0 + 1; ++p) {
+                if (p >= l && p != p0) continue;
                 for (int fk : {1, 5}) {
                     sv_schedule c{};
                     c.mode = SV_PARTITIONED;
                     c.block_qubits = l;
                     c.fuse_k = fk;
-                    c.swap_policy = pol;
+                    c.swap_policy = SV_SWAP_LOOKAHEAD;
                     c.remap = SV_REMAP_VIRTUAL;
                     c.diag_free = 1;
                     c.reg_qubits = std::min(r, l);
+                    c.pin_qubits = p;
                     out.push_back(c);
                 }
+            }
         }
     return out;
 }

@@ -36,10 +36,14 @@ NP_DTYPE = {SV_COMPLEX64: np.complex64, SV_COMPLEX128: np.complex128}
 
 
 class SvError(RuntimeError):
-    def __init__(self, status: int, message: str):
-        super().__init__(f"sv status {status}: {message}")
+    def __init__(self, status: int, message: str = ""):
+        # args = (status, message): the error pickles (worker processes)
+        super().__init__(status, message)
         self.status = status
         self.message = message
+
+    def __str__(self):
+        return f"sv status {self.status}: {self.message}"
 
 
 class sv_schedule(ctypes.Structure):

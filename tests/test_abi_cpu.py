@@ -176,13 +176,14 @@ def test_empty_and_swap_only_circuits():
 def test_tuner_candidates():
     c = sv.sv_tune_candidates(30, "c64")
     assert len(c) == 24
-    got = {(x.block_qubits, x.reg_qubits, x.swap_policy, x.fuse_k) for x in c}
-    assert got == {(l, r, p, f) for l in (11, 12, 13) for r in (4, 5) for p in (0, 1) for f in (1, 5)}
-    assert all(x.mode == sv.SV_PARTITIONED and x.tuner == 0 for x in c)
+    got = {(x.block_qubits, x.reg_qubits, x.pin_qubits, x.fuse_k) for x in c}
+    assert got == {(l, r, p, f) for l in (12, 13, 14) for r in (4, 5) for p in (4, 5) for f in (1, 5)}
+    assert all(x.mode == sv.SV_PARTITIONED and x.tuner == 0 and x.swap_policy == sv.SV_SWAP_LOOKAHEAD for x in c)
     c = sv.sv_tune_candidates(30, "c128")
-    assert {(x.block_qubits, x.reg_qubits) for x in c} == {(l, r) for l in (10, 11, 12) for r in (3, 4)}
+    assert {(x.block_qubits, x.reg_qubits, x.pin_qubits) for x in c} == \
+        {(l, r, p) for l in (11, 12, 13) for r in (3, 4) for p in (3, 4)}
     small = sv.sv_tune_candidates(3, "c64")
-    assert all(x.reg_qubits <= x.block_qubits <= 3 for x in small) and len(small) == 12
+    assert all(x.reg_qubits <= x.block_qubits <= 3 for x in small) and len(small) == 6
     with pytest.raises(sv.SvError):
         sv.sv_tune_candidates(0, "c64")
 
