@@ -306,6 +306,8 @@ def main():
                 ("c128-plain", "c128", sv.schedule("plain"), 1, 1),
                 ("c128-partitioned", "c128", sv.schedule(), 3, 1),
                 ("c64-partitioned-l13-defaults", "c64", sv.schedule(block_qubits=13), 4, 2),
+                ("c64-fused-k5-mfma", "c64",
+                 sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, fuse_k=5), 2, 1),
                 ("c64-partitioned-outer-tier-l2-25", "c64",
                  sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, outer_qubits=25), 4, 2),
                 ("c64-plain", "c64", sv.schedule("plain"), 1, 1),

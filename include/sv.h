@@ -295,7 +295,7 @@ sv_status sv_jit_precompile(int n, sv_dtype dtype, const sv_gate *gates, size_t 
  *   1 bytes per amplitude      9 plain sweeps
  *   2 block qubits l          10 log2 of the algorithmic bytes of all passes
  *   3 register qubits         11 device ops over all block passes
- *   4 swap policy (1 = LA)    12 most ops in one block pass
+ *   4 pinned low qubits       12 most ops in one block pass
  *   5 fuse_k                  13 dense ops (H, X, 2x2)
  *   6 non-SWAP gates          14 diagonal ops (phase, diag, diagonal run)
  *   7 block passes            15 layout ops (register/LDS re-layouts) */

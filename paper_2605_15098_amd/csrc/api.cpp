@@ -887,7 +887,12 @@ void plan_features(int n, int dtype, const svp::PlanConfig &c, const svp::Plan &
     f[1] = (float)amp_bytes(dtype);
     f[2] = (float)(c.mode == 1 ? p.l : 0);
     f[3] = (float)logr;
-    f[4] = (float)(c.policy == SV_SWAP_LOOKAHEAD ? 1 : 0);
+    // low memory qubits kept local in every block (virtual remap): the
+    // length of the contiguous runs every access covers
+    int pin = 0;
+    if (c.mode == 1 && c.remap == SV_REMAP_VIRTUAL)
+        pin = std::max(0, std::min(c.pin_low >= 0 ? c.pin_low : (dtype == SV_COMPLEX64 ? 4 : 3), p.l - 1));
+    f[4] = (float)pin;
     f[5] = (float)c.fuse_k;
     f[6] = (float)p.stats.gates;
     f[7] = (float)k2;

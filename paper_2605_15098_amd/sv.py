@@ -346,7 +346,7 @@ def sv_tune(h, gates, mode=SV_TUNER_EXHAUSTIVE) -> sv_schedule:
 
 
 SV_FEATURES = 16
-FEATURE_NAMES = ["n", "bytes_per_amp", "block_qubits", "reg_qubits", "lookahead", "fuse_k", "gates",
+FEATURE_NAMES = ["n", "bytes_per_amp", "block_qubits", "reg_qubits", "pin_qubits", "fuse_k", "gates",
                  "block_passes", "swap_passes", "plain_sweeps", "log2_bytes", "ops", "max_pass_ops",
                  "dense_ops", "diag_ops", "layout_ops"]
 

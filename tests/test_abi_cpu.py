@@ -194,7 +194,7 @@ def test_features_agree_with_the_plan():
             f = sv.sv_features(n, "c64", g, c)
             st = sv.sv_plan(n, "c64", g, c)
             assert f[0] == n and f[1] == 8 and f[2] == c.block_qubits
-            assert f[3] == c.reg_qubits and f[4] == (c.swap_policy == sv.SV_SWAP_LOOKAHEAD)
+            assert f[3] == c.reg_qubits and f[4] == c.pin_qubits
             assert f[6] == st["gates"] and f[7] == st["passes"]
             assert f[10] == pytest.approx(np.log2(st["bytes"]), abs=1e-4)
             assert f[13] + f[14] + f[15] <= f[11] and f[12] <= f[11]

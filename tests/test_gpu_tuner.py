@@ -40,16 +40,17 @@ def passes_model():
     return mlp.pack(t, 16).astype(np.float32)
 
 
-@pytest.mark.parametrize("dtype,reg", [("c64", 3), ("c64", 5), ("c128", 3)])
-def test_register_tile_schedules_match_oracle(dtype, reg):
-    rng = np.random.default_rng(60 + reg)
-    n = 14
+@pytest.mark.parametrize("dtype,reg,pin", [("c64", 3, 0), ("c64", 5, 0), ("c128", 3, 0), ("c64", 5, 5),
+                                           ("c64", 4, 6), ("c128", 4, 4)])
+def test_register_tile_and_pin_schedules_match_oracle(dtype, reg, pin):
+    rng = np.random.default_rng(60 + reg + 7 * pin)
+    n = 15
     g = W.random_mixed_circuit(n, 120, rng)
     want = oracle.apply(n, g)
-    for l in (9, 12):
-        log(f"case reg_qubits={reg} l={l} dtype={dtype}")
+    for l in (9, 12, 14 if dtype == "c64" else 13):
+        log(f"case reg_qubits={reg} pin_qubits={pin} l={l} dtype={dtype}")
         s = sv.StateVector(n, dtype)
-        s.apply(g, sv.schedule(block_qubits=l, reg_qubits=reg))
+        s.apply(g, sv.schedule(block_qubits=l, reg_qubits=reg, pin_qubits=pin))
         got = s.state()
         s.close()
         assert np.max(np.abs(got - want)) <= TOL[dtype]
