@@ -305,7 +305,8 @@ def main():
         for name, dt, sch, st_, wu in (
                 ("c128-plain", "c128", sv.schedule("plain"), 1, 1),
                 ("c128-partitioned", "c128", sv.schedule(), 3, 1),
-                ("c64-partitioned-l13-defaults", "c64", sv.schedule(block_qubits=13), 4, 2),
+                ("c64-partitioned-l13-pin4-reg4", "c64", sv.schedule(block_qubits=13, pin_qubits=4, reg_qubits=4),
+                 4, 2),
                 ("c64-fused-k5-mfma", "c64",
                  sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, fuse_k=5), 2, 1),
                 ("c64-partitioned-outer-tier-l2-25", "c64",

@@ -94,7 +94,8 @@ enum { SV_TUNER_NONE = 0, SV_TUNER_EXHAUSTIVE = 1, SV_TUNER_LEARNED = 2 };
 typedef struct {
     int32_t mode;         /* SV_PLAIN: one sweep per gate (Algorithm 1);
                              SV_PARTITIONED: Section III-B                     */
-    int32_t block_qubits; /* l, local qubits per on-chip block; 0 = default   */
+    int32_t block_qubits; /* l, local qubits per on-chip block; 0 = default
+                             (14 for complex64, 13 for complex128)           */
     int32_t outer_qubits; /* l2 (0 = off): outer tier. Consecutive block
                              passes whose local qubits together number at
                              most l2 run outer block by outer block (2^l2
@@ -120,12 +121,12 @@ typedef struct {
     int32_t tuner;        /* SV_TUNER_*: sv_apply_circuit first picks the
                              schedule itself (sv_tune); NONE = use this one   */
     int32_t reg_qubits;   /* amplitudes per thread in a block pass = 2^this;
-                             0 = default (4)                                  */
+                             0 = default (5 for complex64, 4 for complex128) */
     int32_t pin_qubits;   /* low physical qubits local in every block with
                              virtual remap: contiguous runs of 2^this
-                             amplitudes per access; 0 = default (4 for
-                             complex64 = 128-byte segments, 3 for
-                             complex128); more pins leave fewer free local
+                             amplitudes per access; 0 = default (5 for
+                             complex64 = 256-byte runs, 3 for complex128 =
+                             128-byte runs); more pins leave fewer free local
                              qubits per pass                                  */
 } sv_schedule;
 

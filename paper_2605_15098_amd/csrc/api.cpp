@@ -891,7 +891,7 @@ void plan_features(int n, int dtype, const svp::PlanConfig &c, const svp::Plan &
     // length of the contiguous runs every access covers
     int pin = 0;
     if (c.mode == 1 && c.remap == SV_REMAP_VIRTUAL)
-        pin = std::max(0, std::min(c.pin_low >= 0 ? c.pin_low : (dtype == SV_COMPLEX64 ? 4 : 3), p.l - 1));
+        pin = std::max(0, std::min(c.pin_low >= 0 ? c.pin_low : svp::default_pin_qubits(dtype), p.l - 1));
     f[4] = (float)pin;
     f[5] = (float)c.fuse_k;
     f[6] = (float)p.stats.gates;

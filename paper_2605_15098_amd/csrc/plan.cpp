@@ -16,8 +16,13 @@ int amp_bytes(int dtype) { return dtype == 0 ? 8 : 16; }
 int segment_bits(int dtype) { return dtype == 0 ? 4 : 3; }
 }  // namespace
 
-int default_block_qubits(int dtype) { return dtype == 0 ? 13 : 12; }
+// Defaults measured on the 32-qubit QPE (the largest blocks, 256-byte runs
+// and 32 amplitudes per thread for complex64; 128-byte runs and 16 per
+// thread for complex128).
+int default_block_qubits(int dtype) { return dtype == 0 ? 14 : 13; }
 int max_block_qubits(int dtype) { return dtype == 0 ? 14 : 13; }
+int default_pin_qubits(int dtype) { return dtype == 0 ? 5 : 3; }
+int default_reg_qubits(int dtype) { return dtype == 0 ? 5 : 4; }
 
 bool gate_matrix(int op, double theta, const double *u_in, double *u, int *cls)
 {
@@ -653,13 +658,13 @@ std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
     }
     if (l > max_block_qubits(cfg.dtype)) return "block_qubits above the on-chip maximum";
     b.l = l;
-    b.logr = std::min(cfg.logr, l);
+    b.logr = std::min(cfg.logr > 0 ? cfg.logr : default_reg_qubits(cfg.dtype), l);
     if (l - b.logr > 10) b.logr = l - 10;  // at most 1024 threads per block
     plan.l = l;
     const bool explicit_remap = cfg.remap == 1;
     int pin = 0;
     if (!explicit_remap) {
-        pin = cfg.pin_low >= 0 ? cfg.pin_low : b.sbits;
+        pin = cfg.pin_low >= 0 ? cfg.pin_low : default_pin_qubits(cfg.dtype);
         pin = std::min(pin, l - 1);
         if (pin < 0) pin = 0;
     }

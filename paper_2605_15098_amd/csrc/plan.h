@@ -74,7 +74,7 @@ struct PlanConfig {
     int dtype = 0;            // 0 = complex64, 1 = complex128
     int mode = 1;             // 0 plain, 1 partitioned
     int l = 0;                // block qubits (0 = default)
-    int logr = 4;             // register bits per thread
+    int logr = 0;             // register bits per thread (0 = default for the dtype)
     int policy = 0;           // 0 LRU, 1 look-ahead
     int remap = 0;            // 0 virtual, 1 explicit
     int diag_free = 0;        // diagonal gates never force a SWAP
@@ -100,6 +100,10 @@ struct Plan {
 // Default block size for a dtype (complex64 / complex128).
 int default_block_qubits(int dtype);
 int max_block_qubits(int dtype);
+// Default low memory qubits kept in every block (virtual remap) and default
+// register qubits per thread.
+int default_pin_qubits(int dtype);
+int default_reg_qubits(int dtype);
 
 // Build the 2x2 FP64 matrix and class of a gate. Returns false for an
 // unknown op.

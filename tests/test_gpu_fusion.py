@@ -45,7 +45,7 @@ def test_fused_random_circuits_match_oracle(n, l, fuse, dtype):
     psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     psi0 /= np.linalg.norm(psi0)
     log(f"case fused random n={n} l={l} k={fuse} dtype={dtype}")
-    got, st = run(n, dtype, g, sv.schedule(block_qubits=l, fuse_k=fuse), psi0)
+    got, st = run(n, dtype, g, sv.schedule(block_qubits=l, fuse_k=fuse, reg_qubits=4), psi0)
     assert (st["fused"] > 0) == (l - 4 >= 6)
     assert np.max(np.abs(got - oracle.apply(n, g, psi0))) <= TOL[dtype]
 

@@ -153,7 +153,7 @@ def test_dense_fusion_programs(n, l, dtype, fuse):
     got, _ = run(n, W.qpe_gates(n, phi), dtype=dtype, l=l, fuse=fuse)
     assert np.max(np.abs(got - cf.qpe_state(n, phi))) < tol
     st = sv.sv_plan(n, "c64" if dtype == 0 else "c128", W.qpe_gates(n, phi),
-                    sv.schedule(block_qubits=l, fuse_k=fuse))
+                    sv.schedule(block_qubits=l, fuse_k=fuse, reg_qubits=4))
     # matrix-core windows need blocks of at least 64 threads (2^(l - 4))
     assert (st["fused"] > 0) == (l - 4 >= 6)
 
