@@ -36,10 +36,12 @@ def test_batch_qpe_matches_single_and_closed_form(dtype):
     l = 9
     batch = make(ns, dtype)
     log(f"case batch qpe dtype={dtype}")
-    sv.sv_apply_batch([s.h for s in batch], gl, sv.schedule(block_qubits=l))
+    # batched passes run 2^3 or 2^4 amplitudes per thread; the single runs use the same tile
+    sched = sv.schedule(block_qubits=l, reg_qubits=4)
+    sv.sv_apply_batch([s.h for s in batch], gl, sched)
     for i, (n, p) in enumerate(zip(ns, phis)):
         single = sv.StateVector(n, dtype)
-        single.apply(gl[i], sv.schedule(block_qubits=l))
+        single.apply(gl[i], sched)
         a, b = batch[i].state(), single.state()
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (i, n)
         assert np.max(np.abs(a - cf.qpe_state(n, p))) <= TOL[dtype]
@@ -56,7 +58,7 @@ def test_batch_replay_accumulates_and_random_circuits():
     gl = [W.random_mixed_circuit(n, 60, rng, with_swap=True) for n in ns]
     batch = make(ns, "c128")
     ref = make(ns, "c128")
-    sched = sv.schedule(block_qubits=10)
+    sched = sv.schedule(block_qubits=10, reg_qubits=4)
     for rep in range(3):  # the second call of each layout replays a cached graph
         log(f"case batch replay {rep}")
         sv.sv_apply_batch([s.h for s in batch], gl, sched)
