@@ -335,10 +335,30 @@ struct Builder {
         }
     }
 
+    // LDS of one work-group on gfx950.
+    static constexpr uint32_t kLdsLimit = 160 * 1024;
+
+    // A block pass whose factor tables would not fit in LDS next to the
+    // block is compiled again with one op per diagonal gate (no tables).
     void compile_block(const std::vector<MGate> &q, const std::vector<int> &B)
+    {
+        const size_t ops0 = plan.ops.size(), tab0 = plan.table.size(), steps0 = plan.steps.size();
+        const PlanStats st0 = plan.stats;
+        compile_block_impl(q, B, true);
+        const Step &s = plan.steps.back();
+        if (k2_lds_layout(s.l, ab, s.nug, s.tab_count, s.nut).total <= kLdsLimit) return;
+        plan.ops.resize(ops0);
+        plan.table.resize(tab0);
+        plan.steps.resize(steps0);
+        plan.stats = st0;
+        compile_block_impl(q, B, false);
+    }
+
+    void compile_block_impl(const std::vector<MGate> &q, const std::vector<int> &B, bool tables)
     {
         const int r = logr;
         const bool combine = cfg.fuse_k >= 1;
+        const bool combine_diag = combine && tables;
         ptab.clear();
         std::vector<int> rank(64, -1);
         for (int i = 0; i < (int)B.size(); ++i) rank[B[i]] = i;
@@ -407,7 +427,7 @@ struct Builder {
         std::vector<MGate> pending;
         auto flush_diag = [&]() {
             if (pending.empty()) return;
-            if (!combine) {
+            if (!combine_diag) {
                 for (const MGate &g : pending) emit_single_diag(g);
             } else {
                 std::vector<MGate> unit_run;

@@ -182,3 +182,14 @@ def test_generated_pass_kernels_compile(case, dtype):
     gg = np.ascontiguousarray(g)
     cnt = emu().emu_jit_check(n, dtype, l, logr, 1, 0, 1, fuse, gg.ctypes.data, len(gg), buf, len(buf))
     assert cnt > 0, buf.value.decode(errors="replace")[:4000]
+
+
+def test_fused_qpe32_passes_fit_lds():
+    """With dense windows the diagonal runs between windows multiply; a pass
+    whose factor tables would overflow the 160 KiB of LDS next to a 2^14
+    block is recompiled without tables. Every generated kernel must compile
+    (the compiler rejects a kernel over the LDS limit)."""
+    g = np.ascontiguousarray(W.qpe_gates(32, 0.16024283037476805))
+    buf = ctypes.create_string_buffer(1 << 16)
+    cnt = emu().emu_jit_check(32, 0, 14, 5, 1, 0, 1, 5, g.ctypes.data, len(g), buf, len(buf))
+    assert cnt > 0, buf.value.decode(errors="replace")[:2000]
