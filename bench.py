@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--block", type=int, default=-1, help="block qubits (default: 14 for c64, library default for c128)")
     ap.add_argument("--pin", type=int, default=-1, help="pinned low qubits (default: 5 for c64)")
     ap.add_argument("--reg", type=int, default=-1, help="register qubits per thread (default: 5 for c64)")
+    ap.add_argument("--policy", default="graph", choices=("graph", "lookahead", "lru"),
+                    help="gate order and block gathering (default: over the dependence graph)")
     ap.add_argument("--quick", action="store_true", help="skip comparison runs and CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -232,7 +234,7 @@ def main():
     block = args.block if args.block >= 0 else (14 if c64 else 0)
     pin = args.pin if args.pin >= 0 else (5 if c64 else 0)
     reg = args.reg if args.reg >= 0 else (5 if c64 else 0)
-    sched = sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg)
+    sched = sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, swap_policy=args.policy)
 
     log(f"workload qpe n={n} dtype={args.dtype} phi_seed={seed} gates={ngates}")
     sim = sv.StateVector(n, args.dtype)
@@ -269,7 +271,7 @@ def main():
             "gates_per_step": ngates, "swap_relabels": (n - 1) // 2,
             "schedule": {"mode": "partitioned", "block_qubits": st["block_qubits"],
                          "pin_qubits": pin or "default", "reg_qubits": reg or "default",
-                         "swap_policy": "lookahead-bulk", "remap": "virtual", "diag_free": True},
+                         "swap_policy": args.policy, "remap": "virtual", "diag_free": True},
             "passes_per_step": st["passes"], "swaps_per_step": st["swaps"],
         },
         "effective_GBps": eff_gbps,
@@ -282,7 +284,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": k2_achieved / HBM_PEAK_GBPS,
-            "traffic": measured_traffic("k2", f"qpe{n}-{args.dtype}-l{st['block_qubits']}p{pin}r{reg}"),
+            "traffic": measured_traffic("k2", f"qpe{n}-{args.dtype}-{args.policy}-l{st['block_qubits']}p{pin}r{reg}"),
             "algorithmic_bytes_per_launch": pass_bytes,
             "launches": kl[1],
             "avg_launch_ms": kms[1] / kl[1] if kl[1] else None,
@@ -307,6 +309,8 @@ def main():
                 ("c128-partitioned", "c128", sv.schedule(), 3, 1),
                 ("c64-partitioned-l13-pin4-reg4", "c64", sv.schedule(block_qubits=13, pin_qubits=4, reg_qubits=4),
                  4, 2),
+                ("c64-lookahead-circuit-order", "c64",
+                 sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, swap_policy="lookahead"), 4, 2),
                 ("c64-fused-k5-mfma", "c64",
                  sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, fuse_k=5), 2, 1),
                 ("c64-partitioned-outer-tier-l2-25", "c64",

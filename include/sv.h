@@ -12,7 +12,8 @@
  * applied block by block while the block stays on chip; a gate whose target is
  * global first brings that qubit into the block in place of a local one chosen
  * by LRU (or by a look-ahead policy), and a global control is decided per
- * block.
+ * block. By default gates are not taken in list order but in any order their
+ * dependences allow (SV_SWAP_GRAPH), which gathers more gates per block.
  *
  * Conventions
  *   - Qubit q is bit q of the amplitude index (little-endian).
@@ -83,7 +84,19 @@ typedef struct {
 
 /* Schedule modes and options. */
 enum { SV_PLAIN = 0, SV_PARTITIONED = 1 };
-enum { SV_SWAP_LRU = 0, SV_SWAP_LOOKAHEAD = 1 };
+enum {
+    SV_SWAP_LRU = 0,       /* Section III-B: gates in circuit order, the victim
+                              is the least recently used local qubit         */
+    SV_SWAP_LOOKAHEAD = 1, /* gates in circuit order; at a forced flush the
+                              next block gathers the qubits that the upcoming
+                              gates target first                             */
+    SV_SWAP_GRAPH = 2      /* gates in any order their dependences allow (two
+                              gates are ordered only when they share a qubit
+                              on which one of them is not diagonal; circuit
+                              SWAPs become renames); each block gathers the
+                              qubits that let the longest chains of gates
+                              proceed. Virtual remap only                    */
+};
 enum {
     SV_REMAP_VIRTUAL = 0, /* a SWAP moves no data: the next block pass gathers
                              the new local qubits by address (zero bytes)     */
@@ -113,7 +126,7 @@ typedef struct {
                              amplitude and Hadamard normalization is applied
                              once per pass; 2..6: also fuse runs of gates on
                              <= k qubits into one 2^k x 2^k unitary            */
-    int32_t swap_policy;  /* SV_SWAP_LRU (the paper) or SV_SWAP_LOOKAHEAD     */
+    int32_t swap_policy;  /* SV_SWAP_LRU (the paper), _LOOKAHEAD or _GRAPH     */
     int32_t remap;        /* SV_REMAP_VIRTUAL or SV_REMAP_EXPLICIT            */
     int32_t diag_free;    /* 0: every gate's target must be local (the paper's
                              rule); 1: diagonal gates (Z, P, RZ and their
@@ -179,7 +192,9 @@ sv_status sv_reset(sv_handle h);
 sv_status sv_set_stream(sv_handle h, void *hip_stream);
 
 /* Apply m gates in order to the current state (calls accumulate). The
- * schedule may be NULL (= partitioned, defaults). The physical layout may
+ * schedule may be NULL (= partitioned, SV_SWAP_GRAPH, virtual remap,
+ * diagonal gates free, the other fields at their defaults). The physical
+ * layout may
  * stay permuted between calls; readouts undo it. Stream-ordered: returns
  * once the work is queued. Errors: INVALID_ARG (target >= n, control ==
  * target, non-finite theta, unknown op, SWAP with a control), UNSUPPORTED
@@ -249,8 +264,8 @@ sv_status sv_plan(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const s
 /* ---- schedule tuning (the paper sweeps the block size by hand over a
  * range and keeps the median of three runs, Section IV-B) ----
  *
- * Candidates: partitioned schedules with look-ahead bulk remap (virtual) and
- * diagonal gates free, over
+ * Candidates: partitioned schedules over the dependence graph
+ * (SV_SWAP_GRAPH, virtual remap) with diagonal gates free, over
  *   block qubits  the three largest sizes that fit on chip (complex64 12..14,
  *                 complex128 11..13; capped at n),
  *   register tile 2^4 or 2^5 amplitudes per thread (complex64),
@@ -259,8 +274,9 @@ sv_status sv_plan(int n, sv_dtype dtype, const sv_gate *gates, size_t m, const s
  *   fusion        fuse_k 1 (diagonal runs combined) or 5 (also dense windows
  *                 of up to 5 qubits through the matrix cores)
  * (a block smaller than the register tile is one tile). The paper's LRU
- * placement is left out: it never came within a factor of two of look-ahead
- * on the measured circuits. sv_tune_candidates writes up to cap of them to
+ * placement and list-order look-ahead are left out: on the measured circuits
+ * they need more block passes than the dependence-graph schedule (LRU never
+ * came within a factor of two of look-ahead). sv_tune_candidates writes up to cap of them to
  * out (out may be NULL) and their number to *count (24 when n is at least
  * the largest size). */
 sv_status sv_tune_candidates(int n, sv_dtype dtype, sv_schedule *out, int cap, int *count);

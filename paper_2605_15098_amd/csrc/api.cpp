@@ -185,7 +185,7 @@ svp::PlanConfig config_from(sv_handle h, const sv_schedule *s)
     if (!s) {
         c.mode = 1;
         c.l = 0;
-        c.policy = SV_SWAP_LOOKAHEAD;
+        c.policy = SV_SWAP_GRAPH;
         c.remap = SV_REMAP_VIRTUAL;
         c.diag_free = 1;
         c.fuse_k = 1;
@@ -211,10 +211,12 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
     if (s->block_qubits < 0) return fail(SV_ERR_INVALID_ARG, "block_qubits < 0");
     if (s->block_qubits > svp::max_block_qubits(dtype))
         return fail(SV_ERR_UNSUPPORTED, "block_qubits above the on-chip maximum for this dtype");
-    if (s->swap_policy != SV_SWAP_LRU && s->swap_policy != SV_SWAP_LOOKAHEAD)
+    if (s->swap_policy != SV_SWAP_LRU && s->swap_policy != SV_SWAP_LOOKAHEAD && s->swap_policy != SV_SWAP_GRAPH)
         return fail(SV_ERR_INVALID_ARG, "unknown swap policy");
     if (s->remap != SV_REMAP_VIRTUAL && s->remap != SV_REMAP_EXPLICIT)
         return fail(SV_ERR_INVALID_ARG, "unknown remap");
+    if (s->swap_policy == SV_SWAP_GRAPH && s->remap != SV_REMAP_VIRTUAL && s->mode == SV_PARTITIONED)
+        return fail(SV_ERR_UNSUPPORTED, "the dependence-graph schedule needs virtual remap");
     if (s->fuse_k < 0) return fail(SV_ERR_INVALID_ARG, "fuse_k < 0");
     if (s->fuse_k > 6) return fail(SV_ERR_UNSUPPORTED, "fuse_k above 6");
     if (s->fuse_k == 2 || s->fuse_k == 3 || s->fuse_k == 6)
@@ -843,7 +845,7 @@ std::vector<sv_schedule> candidates(int n, int dtype)
                     c.mode = SV_PARTITIONED;
                     c.block_qubits = l;
                     c.fuse_k = fk;
-                    c.swap_policy = SV_SWAP_LOOKAHEAD;
+                    c.swap_policy = SV_SWAP_GRAPH;
                     c.remap = SV_REMAP_VIRTUAL;
                     c.diag_free = 1;
                     c.reg_qubits = std::min(r, l);
@@ -1492,7 +1494,7 @@ sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, 
         h->st.block_qubits = e->l;
         h->st.mode = 1;
         h->st.fuse_k = s ? s->fuse_k : 1;
-        h->st.swap_policy = s ? s->swap_policy : SV_SWAP_LOOKAHEAD;
+        h->st.swap_policy = s ? s->swap_policy : SV_SWAP_GRAPH;
         h->timed = false;
     }
     return SV_OK;
@@ -1534,7 +1536,7 @@ sv_status sv_tune_batch(sv_handle *hs, int count, const sv_gate *const *gates, c
                 c.mode = SV_PARTITIONED;
                 c.block_qubits = l;
                 c.fuse_k = fuse;
-                c.swap_policy = SV_SWAP_LOOKAHEAD;
+                c.swap_policy = SV_SWAP_GRAPH;
                 c.remap = SV_REMAP_VIRTUAL;
                 c.diag_free = 1;
                 std::vector<double> t;

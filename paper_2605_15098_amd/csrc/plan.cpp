@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <queue>
 #include <limits>
 
 namespace svp {
@@ -633,6 +635,164 @@ struct Builder {
     }
 };
 
+// Partitioned schedule over the gate dependence graph (virtual remap only).
+//
+// Circuit SWAPs are relabels, so they are taken out first: every later gate
+// is renamed onto the memory bits the SWAPs leave its qubits on. Two of the
+// remaining gates are ordered only when they share a qubit on which at least
+// one of them is not diagonal (a control and a diagonal gate act diagonally
+// on their qubits); gates that are diagonal on every qubit they share
+// commute, so any order the graph allows gives the same state up to
+// rounding. Deferral then works on the graph instead of the list: every
+// ready gate whose target is local (or that needs no local target) joins the
+// current block pass, lowest circuit index first, and when only gates with
+// a global target are ready the pass is flushed and the next block's local
+// qubits are chosen by look-ahead: starting from the pinned bits, the target
+// of the ready gate with the longest chain of dependent local-target gates
+// is added, everything that the bits chosen so far let run is run on a copy
+// of the graph, and this repeats until the block is full.
+std::string schedule_graph(const PlanConfig &cfg, const RawGate *gates, size_t m, int l, int pin, Plan &plan, std::vector<int> &l2p, std::vector<int> &slot_mem,
+                           std::vector<int> &mem_slot, std::vector<MGate> &queue,
+                           const std::function<void()> &flush)
+{
+    std::vector<MGate> G;
+    G.reserve(m);
+    for (size_t i = 0; i < m; ++i) {
+        const RawGate &x = gates[i];
+        if (x.op == OP_SWAP) {
+            std::swap(l2p[x.target], l2p[x.target2]);
+            continue;
+        }
+        MGate g;
+        g.op = x.op;
+        gate_matrix(x.op, x.theta, x.u, g.u, &g.cls);
+        g.t = l2p[x.target];
+        g.c = x.control >= 0 ? l2p[x.control] : -1;
+        diag_angles(x, g);
+        G.push_back(g);
+    }
+    const int M = (int)G.size();
+    std::vector<int> indeg(M, 0), prio(M, 0);
+    std::vector<std::vector<int>> succ(M);
+    std::vector<char> blocking(M);
+    {
+        std::vector<int> last_nd(64, -1);
+        std::vector<std::vector<int>> diag_since(64);
+        auto edge = [&](int a, int c) {
+            succ[a].push_back(c);
+            ++indeg[c];
+        };
+        for (int i = 0; i < M; ++i) {
+            const MGate &g = G[i];
+            blocking[i] = !(cfg.diag_free && g.cls == GC_DIAG);
+            const int qs[2] = {g.t, g.c};
+            const bool nd[2] = {g.cls != GC_DIAG, false};
+            for (int k = 0; k < 2; ++k) {
+                const int q = qs[k];
+                if (q < 0) continue;
+                if (last_nd[q] >= 0) edge(last_nd[q], i);
+                if (nd[k]) {
+                    for (int d : diag_since[q]) edge(d, i);
+                    diag_since[q].clear();
+                    last_nd[q] = i;
+                } else {
+                    diag_since[q].push_back(i);
+                }
+            }
+        }
+    }
+    // longest chain of local-target gates starting at each gate
+    for (int i = M - 1; i >= 0; --i) {
+        int best = 0;
+        for (int s : succ[i]) best = std::max(best, prio[s]);
+        prio[i] = best + blocking[i];
+    }
+    auto runnable = [&](int i, const std::vector<char> &local) { return !blocking[i] || local[G[i].t]; };
+
+    // look-ahead choice of the next block's free local bits from the ready set
+    auto choose = [&](const std::vector<int> &ready) {
+        std::vector<char> in(64, 0);
+        for (int p = 0; p < pin; ++p) in[p] = 1;
+        std::vector<int> want, work = ready, held, undo;
+        for (;;) {
+            while (!work.empty()) {
+                const int i = work.back();
+                work.pop_back();
+                if (!runnable(i, in)) {
+                    held.push_back(i);
+                    continue;
+                }
+                for (int s : succ[i]) {
+                    undo.push_back(s);
+                    if (--indeg[s] == 0) work.push_back(s);
+                }
+            }
+            if (held.empty() || pin + (int)want.size() >= l) break;
+            int best = -1;
+            for (int i : held)
+                if (best < 0 || prio[i] > prio[best] || (prio[i] == prio[best] && i < best)) best = i;
+            in[G[best].t] = 1;
+            want.push_back(G[best].t);
+            work.swap(held);
+        }
+        for (int s : undo) ++indeg[s];
+        return want;
+    };
+    // gather the chosen bits, keeping the pinned bits and, in the places left,
+    // the bits already local; new bits take the freed slots in slot order
+    auto gather = [&](const std::vector<int> &want) {
+        std::vector<char> keep(64, 0);
+        int kept = 0;
+        for (int p = 0; p < pin; ++p) keep[p] = 1, ++kept;
+        for (int p : want) keep[p] = 1, ++kept;
+        for (int v = 0; v < l && kept < l; ++v)
+            if (!keep[slot_mem[v]]) keep[slot_mem[v]] = 1, ++kept;
+        std::vector<int> incoming;
+        for (int p : want)
+            if (mem_slot[p] < 0) incoming.push_back(p);
+        size_t next = 0;
+        for (int v = 0; v < l && next < incoming.size(); ++v) {
+            if (keep[slot_mem[v]]) continue;
+            mem_slot[slot_mem[v]] = -1;
+            slot_mem[v] = incoming[next++];
+            mem_slot[slot_mem[v]] = v;
+            plan.stats.swaps += 1;
+        }
+        std::vector<char> local(64, 0);
+        for (int v = 0; v < l; ++v) local[slot_mem[v]] = 1;
+        return local;
+    };
+
+    std::priority_queue<int, std::vector<int>, std::greater<int>> ready;
+    std::vector<int> held;
+    for (int i = 0; i < M; ++i)
+        if (indeg[i] == 0) held.push_back(i);
+    // the first block costs nothing to choose either
+    std::vector<char> local = gather(choose(held));
+    for (;;) {
+        for (int i : held) ready.push(i);
+        held.clear();
+        while (!ready.empty()) {
+            const int i = ready.top();
+            ready.pop();
+            if (!runnable(i, local)) {
+                held.push_back(i);
+                continue;
+            }
+            queue.push_back(G[i]);
+            plan.stats.gates += 1;
+            for (int s : succ[i])
+                if (--indeg[s] == 0) ready.push(s);
+        }
+        if (held.empty()) break;
+        flush();
+        local = gather(choose(held));
+    }
+    flush();
+    plan.l2p_after = l2p;
+    return "";
+}
+
 }  // namespace
 
 std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
@@ -708,6 +868,11 @@ std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
         b.compile_block(queue, B);
         queue.clear();
     };
+
+    if (cfg.policy == 2) {
+        if (explicit_remap) return "the dependence-graph schedule needs virtual remap";
+        return schedule_graph(cfg, gates, m, l, pin, plan, l2p, slot_mem, mem_slot, queue, flush);
+    }
 
     // next time (gate index > i) the data now at memory bit p is the target of
     // a gate that needs it local; circuit SWAPs rename it on the way

@@ -26,7 +26,7 @@ SV_OK, SV_ERR_INVALID_ARG, SV_ERR_OUT_OF_MEMORY, SV_ERR_DEVICE, SV_ERR_UNSUPPORT
     SV_ERR_BAD_HANDLE = 0, -1, -2, -3, -4, -5
 SV_COMPLEX64, SV_COMPLEX128 = 0, 1
 SV_PLAIN, SV_PARTITIONED = 0, 1
-SV_SWAP_LRU, SV_SWAP_LOOKAHEAD = 0, 1
+SV_SWAP_LRU, SV_SWAP_LOOKAHEAD, SV_SWAP_GRAPH = 0, 1, 2
 SV_REMAP_VIRTUAL, SV_REMAP_EXPLICIT = 0, 1
 SV_TUNER_NONE, SV_TUNER_EXHAUSTIVE, SV_TUNER_LEARNED = 0, 1, 2
 
@@ -64,14 +64,14 @@ class sv_stats(ctypes.Structure):
                 ("kernel_launches", ctypes.c_int64 * 3)]
 
 
-def schedule(mode="partitioned", block_qubits=0, outer_qubits=0, fuse_k=1, swap_policy="lookahead",
+def schedule(mode="partitioned", block_qubits=0, outer_qubits=0, fuse_k=1, swap_policy="graph",
              remap="virtual", diag_free=True, tuner="none", reg_qubits=0, pin_qubits=0) -> sv_schedule:
     s = sv_schedule()
     s.mode = {"plain": SV_PLAIN, "partitioned": SV_PARTITIONED}.get(mode, mode)
     s.block_qubits = int(block_qubits)
     s.outer_qubits = int(outer_qubits)
     s.fuse_k = int(fuse_k)
-    s.swap_policy = {"lru": SV_SWAP_LRU, "lookahead": SV_SWAP_LOOKAHEAD}.get(swap_policy, swap_policy)
+    s.swap_policy = {"lru": SV_SWAP_LRU, "lookahead": SV_SWAP_LOOKAHEAD, "graph": SV_SWAP_GRAPH}.get(swap_policy, swap_policy)
     s.remap = {"virtual": SV_REMAP_VIRTUAL, "explicit": SV_REMAP_EXPLICIT}.get(remap, remap)
     s.diag_free = int(bool(diag_free))
     s.tuner = {"none": SV_TUNER_NONE, "exhaustive": SV_TUNER_EXHAUSTIVE,

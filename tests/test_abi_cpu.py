@@ -178,7 +178,7 @@ def test_tuner_candidates():
     assert len(c) == 24
     got = {(x.block_qubits, x.reg_qubits, x.pin_qubits, x.fuse_k) for x in c}
     assert got == {(l, r, p, f) for l in (12, 13, 14) for r in (4, 5) for p in (4, 5) for f in (1, 5)}
-    assert all(x.mode == sv.SV_PARTITIONED and x.tuner == 0 and x.swap_policy == sv.SV_SWAP_LOOKAHEAD for x in c)
+    assert all(x.mode == sv.SV_PARTITIONED and x.tuner == 0 and x.swap_policy == sv.SV_SWAP_GRAPH for x in c)
     c = sv.sv_tune_candidates(30, "c128")
     assert {(x.block_qubits, x.reg_qubits, x.pin_qubits) for x in c} == \
         {(l, r, p) for l in (11, 12, 13) for r in (3, 4) for p in (3, 4)}

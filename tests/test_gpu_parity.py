@@ -46,9 +46,12 @@ def schedules(n, dtype):
         out.append((f"paper-strict-l{l}", strict_paper, True))
         out.append((f"lru-virtual-strict-l{l}",
                     sv.schedule(block_qubits=l, swap_policy="lru", diag_free=False, fuse_k=0), True))
-        out.append((f"lookahead-strict-l{l}", sv.schedule(block_qubits=l, fuse_k=0), True))
+        out.append((f"lookahead-strict-l{l}", sv.schedule(block_qubits=l, fuse_k=0, swap_policy="lookahead"), True))
         out.append((f"paper-l{l}", sv.paper_schedule(l), False))
-        out.append((f"lookahead-l{l}", sv.schedule(block_qubits=l), False))
+        out.append((f"lookahead-l{l}", sv.schedule(block_qubits=l, swap_policy="lookahead"), False))
+        # gates reordered over the dependence graph: same state up to rounding
+        out.append((f"graph-strict-l{l}", sv.schedule(block_qubits=l, fuse_k=0), False))
+        out.append((f"graph-l{l}", sv.schedule(block_qubits=l), False))
     return out
 
 
@@ -98,8 +101,9 @@ def test_controls_in_every_position_class(dtype):
     g = np.concatenate([g, extra])
     want = oracle.apply(n, g, init)
     for name, sched in [("plain", sv.schedule("plain")), ("paper-l10", sv.paper_schedule(10)),
-                        ("lookahead-l12", sv.schedule(block_qubits=12)),
-                        ("lookahead-default", None)]:
+                        ("lookahead-l12", sv.schedule(block_qubits=12, swap_policy="lookahead")),
+                        ("graph-l12", sv.schedule(block_qubits=12)),
+                        ("graph-default", None)]:
         log(f"case controls dtype={dtype} schedule={name}")
         got, _, _ = run(n, dtype, g, sched, init)
         assert np.max(np.abs(got - want)) <= TOL[dtype], name

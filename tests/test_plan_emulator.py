@@ -74,6 +74,10 @@ CONFIGS = [
     dict(logr=2), dict(logr=3), dict(logr=5),
     dict(pin=0), dict(pin=5),
 ]
+# gates reordered over the dependence graph
+GRAPH = [dict(policy=2), dict(policy=2, fuse=0), dict(policy=2, diag_free=0), dict(policy=2, pin=0),
+         dict(policy=2, logr=2)]
+CONFIGS += GRAPH
 
 
 @pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: ",".join(f"{k}={v}" for k, v in c.items()) or "default")
@@ -90,7 +94,7 @@ def test_random_circuit_programs(n, l, cfg):
     assert np.max(np.abs(got - want)) < 1e-12
 
 
-@pytest.mark.parametrize("cfg", CONFIGS[:5], ids=lambda c: ",".join(f"{k}={v}" for k, v in c.items()) or "default")
+@pytest.mark.parametrize("cfg", CONFIGS[:5] + GRAPH, ids=lambda c: ",".join(f"{k}={v}" for k, v in c.items()) or "default")
 @pytest.mark.parametrize("n,l,dtype", [(10, 6, 0), (13, 8, 1), (14, 10, 0)])
 def test_qpe_programs(n, l, dtype, cfg):
     phi = W.phi_for_seed(n)
@@ -134,9 +138,10 @@ def test_non_unit_diagonal_u2():
     assert np.max(np.abs(got - want)) < 1e-12
 
 
+@pytest.mark.parametrize("policy", [1, 2])
 @pytest.mark.parametrize("fuse", [4, 5])
 @pytest.mark.parametrize("n,l,dtype", [(6, 4, 1), (10, 6, 1), (12, 10, 1), (13, 13, 0), (14, 10, 0), (15, 11, 1)])
-def test_dense_fusion_programs(n, l, dtype, fuse):
+def test_dense_fusion_programs(n, l, dtype, fuse, policy):
     """Windows of up to `fuse` qubits as one matrix op (the emulator applies
     the operand-ordered table in FP64): complex128 tables hold the FP64
     product, complex64 tables its FP32 rounding."""
@@ -147,10 +152,10 @@ def test_dense_fusion_programs(n, l, dtype, fuse):
     g = W.random_mixed_circuit(n, 120, rng)
     psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     psi0 /= np.linalg.norm(psi0)
-    got, _ = run(n, g, psi0, dtype=dtype, l=l, fuse=fuse)
+    got, _ = run(n, g, psi0, dtype=dtype, l=l, fuse=fuse, policy=policy)
     assert np.max(np.abs(got - oracle.apply(n, g, psi0))) < tol
     phi = W.phi_for_seed(n)
-    got, _ = run(n, W.qpe_gates(n, phi), dtype=dtype, l=l, fuse=fuse)
+    got, _ = run(n, W.qpe_gates(n, phi), dtype=dtype, l=l, fuse=fuse, policy=policy)
     assert np.max(np.abs(got - cf.qpe_state(n, phi))) < tol
     st = sv.sv_plan(n, "c64" if dtype == 0 else "c128", W.qpe_gates(n, phi),
                     sv.schedule(block_qubits=l, fuse_k=fuse, reg_qubits=4))
@@ -158,9 +163,10 @@ def test_dense_fusion_programs(n, l, dtype, fuse):
     assert (st["fused"] > 0) == (l - 4 >= 6)
 
 
+@pytest.mark.parametrize("policy", [1, 2])
 @pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("case", ["qpe", "random", "diag", "strict", "fused"])
-def test_generated_pass_kernels_compile(case, dtype):
+def test_generated_pass_kernels_compile(case, dtype, policy):
     """Every block-pass kernel the run-time compiler writes must compile for
     gfx950 (hipRTC runs without a GPU)."""
     rng = np.random.default_rng(17)
@@ -180,16 +186,54 @@ def test_generated_pass_kernels_compile(case, dtype):
         fuse = 0
     buf = ctypes.create_string_buffer(1 << 16)
     gg = np.ascontiguousarray(g)
-    cnt = emu().emu_jit_check(n, dtype, l, logr, 1, 0, 1, fuse, gg.ctypes.data, len(gg), buf, len(buf))
+    cnt = emu().emu_jit_check(n, dtype, l, logr, policy, 0, 1, fuse, gg.ctypes.data, len(gg), buf, len(buf))
     assert cnt > 0, buf.value.decode(errors="replace")[:4000]
 
 
-def test_fused_qpe32_passes_fit_lds():
+@pytest.mark.parametrize("policy", [1, 2])
+def test_fused_qpe32_passes_fit_lds(policy):
     """With dense windows the diagonal runs between windows multiply; a pass
     whose factor tables would overflow the 160 KiB of LDS next to a 2^14
     block is recompiled without tables. Every generated kernel must compile
     (the compiler rejects a kernel over the LDS limit)."""
     g = np.ascontiguousarray(W.qpe_gates(32, 0.16024283037476805))
     buf = ctypes.create_string_buffer(1 << 16)
-    cnt = emu().emu_jit_check(32, 0, 14, 5, 1, 0, 1, 5, g.ctypes.data, len(g), buf, len(buf))
+    cnt = emu().emu_jit_check(32, 0, 14, 5, policy, 0, 1, 5, g.ctypes.data, len(g), buf, len(buf))
     assert cnt > 0, buf.value.decode(errors="replace")[:2000]
+
+
+def test_graph_schedule_qpe32_block_passes():
+    """On the 32-qubit QPE the dependence-graph schedule lets each block take
+    a qubit's Hadamard-layer gate and its inverse-QFT gate in the same pass:
+    three block passes where circuit order needs five (complex64, 2^14-
+    amplitude blocks, 5 pinned qubits); complex128 (2^13, 3 pinned) also
+    needs three."""
+    g = W.qpe_gates(32, 0.16024283037476805)
+    got = {}
+    for dtype, l in (("c64", 14), ("c128", 13)):
+        for pol in ("lookahead", "graph"):
+            got[dtype, pol] = sv.sv_plan(32, dtype, g, sv.schedule(block_qubits=l, swap_policy=pol))["passes"]
+    assert got["c64", "lookahead"] == 5 and got["c64", "graph"] == 3
+    assert got["c128", "graph"] == 3 < got["c128", "lookahead"]
+
+
+def test_graph_schedule_moves_gates_only_across_commuting_ones():
+    """Circuits built so that reordering is wrong unless it respects the
+    dependences: an X on a control between two controlled gates, a Hadamard
+    between diagonal gates on its qubit, SWAPs between gates on the swapped
+    qubits; blocks far smaller than the circuit force many passes."""
+    rows = []
+    rng = np.random.default_rng(12)
+    n = 10
+    for _ in range(30):
+        a, b, c = (int(x) for x in rng.choice(n, 3, replace=False))
+        th = float(rng.random() * 6.28)
+        rows += [("P", a, b, th), ("X", b, -1, 0.0), ("RX", c, b, th), ("H", a, -1, 0.0),
+                 ("RZ", a, -1, th), ("SWAP", a, -1, 0.0, c), ("X", c, a, 0.0), ("H", c, -1, 0.0)]
+    g = W.gates_from_tuples(rows)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    want = oracle.apply(n, g, psi0)
+    for cfg in (dict(l=4, logr=2, pin=1), dict(l=6, logr=3), dict(l=5, logr=2, fuse=0), dict(l=8, logr=4, pin=3)):
+        got, _ = run(n, g, psi0, policy=2, **cfg)
+        assert np.max(np.abs(got - want)) < 1e-12, cfg
