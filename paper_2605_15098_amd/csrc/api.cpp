@@ -201,6 +201,7 @@ svp::PlanConfig config_from(sv_handle h, const sv_schedule *s)
     }
     if (const char *e = std::getenv("SV_PIN_BITS")) c.pin_low = std::atoi(e);
     if (const char *e = std::getenv("SV_LOGR")) c.logr = std::atoi(e);
+    if (const char *e = std::getenv("SV_HALF_LDS")) c.half_lds = std::atoi(e);
     return c;
 }
 
@@ -309,6 +310,7 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
         a.nut = s.nut;
         a.table = h->dtab;
         a.vec2 = (s.l >= 2 && s.logr >= 2 && s.bits[0] == 0) ? 1 : 0;
+        a.half_lds = s.half_lds;
         for (int i = 0; i < s.l; ++i) a.bits[i] = (int8_t)s.bits[i];
         for (size_t k = 0; k < vary.size(); ++k) a.nbits[k] = (int8_t)vary[k];
         a.nblk_bits = (int32_t)vary.size();
@@ -1266,6 +1268,7 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     std::vector<svp::BatchInst> insts(count);
     std::vector<double> work(count);
     size_t max_lds = 0;
+    bool all_half = true;
     const size_t amp = dtype == 0 ? 8 : 16;
     for (int i = 0; i < count; ++i) {
         const svp::Plan &P = plans[i];
@@ -1296,8 +1299,11 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
             bp.args.tab_count = st.tab_count;
             bp.args.ut_off = st.nut ? (int)(st.ut_off + tb) : 0;
             bp.args.nut = st.nut;
-            max_lds = std::max<size_t>(max_lds, svp::k2_lds_layout(st.l, (int)amp, st.nug, st.tab_count, st.nut).total);
+            max_lds = std::max<size_t>(
+                max_lds, svp::k2_lds_layout(st.l, (int)amp, st.nug, st.tab_count, st.nut, st.half_lds).total);
+            all_half = all_half && st.half_lds;
             bp.args.vec2 = (st.l >= 2 && st.logr >= 2 && st.bits[0] == 0) ? 1 : 0;
+            bp.args.half_lds = st.half_lds;
             std::vector<bool> in(hs[i]->n, false);
             for (int b = 0; b < st.l; ++b) {
                 bp.args.bits[b] = (int8_t)st.bits[b];
@@ -1316,7 +1322,7 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     }
     // resident capacity and work-group groups
     const unsigned threads = 1u << (l - logr);
-    const size_t lds = std::max<size_t>(max_lds, svp::k2_lds_layout(l, (int)amp, 0, 0, 0).total);
+    const size_t lds = std::max<size_t>(max_lds, svp::k2_lds_layout(l, (int)amp, 0, 0, 0, all_half).total);
     bool mfma = false;
     for (const svp::K2Op &op : ops) mfma = mfma || op.kind == svp::K2_MFMA;
     const int per_cu = svk::k6_occupancy(dtype, logr, threads, lds, mfma);

@@ -67,7 +67,7 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
          "    using C = typename CT<T>::type;\n    constexpr int R = 1 << LOGR;\n    (void)R;\n";
     std::vector<int> rb(r);
     rb[0] = 0;
-    for (int j = 1; j < r; ++j) rb[j] = l - r + j;
+    for (int j = 1; j < r; ++j) rb[j] = svp::k2_canon_bit(j, l, r);
     for (int i = 0; i < s.op_count; ++i) {
         const svp::K2Op &op = plan.ops[s.op_begin + i];
         switch (op.kind) {
@@ -81,7 +81,7 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
             for (int j = 0; j < r; ++j) o << (j ? ", " : "") << rb[j];
             o << "}; const int rn[" << r << "] = {";
             for (int j = 0; j < r; ++j) o << (j ? ", " : "") << nrb[j];
-            o << "}; k2_layout<LOGR>(a, cx, ro, rn); }\n";
+            o << "}; k2_layout<LOGR>(a, cx, ro, rn, " << op.b << "); }\n";
             rb = nrb;
             break;
         }
@@ -143,12 +143,18 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
     const bool vec2 = s.l >= 2 && s.logr >= 2 && s.bits[0] == 0;  // as the launcher sets args.vec2
     const unsigned threads = 1u << (l - r);
     const size_t amp = dtype == 0 ? 8 : 16;
-    const size_t lds = svp::k2_lds_layout(l, (int)amp, s.nug, s.tab_count, s.nut).total;
-    o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") svk2_pass_" << idx << "(CT<" << T
-      << ">::type *__restrict__ S, svp::K2Args args) {\n"
+    const size_t lds = svp::k2_lds_layout(l, (int)amp, s.nug, s.tab_count, s.nut, s.half_lds).total;
+    // A pass that stages half the block keeps two work-groups on a CU: the
+    // register budget is that of four waves per SIMD and the next block is not
+    // prefetched (the other work-group computes while one waits). The others
+    // prefetch into a second register set.
+    const bool two = s.half_lds && threads * 2 <= 1024;
+    o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ")";
+    if (two) o << " __attribute__((amdgpu_waves_per_eu(" << (threads / 64 * 2 + 3) / 4 << ")))";
+    o << " svk2_pass_" << idx << "(CT<" << T << ">::type *__restrict__ S, svp::K2Args args) {\n"
       << "  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[" << (lds > 0 ? lds : 16) << "];\n"
-      << "  k2_body<" << T << ", " << r << ", " << (vec2 ? "true" : "false") << ", true>(S, args, lds_raw, Prog" << idx
-      << "{}, blockIdx.x, gridDim.x);\n}\n";
+      << "  k2_body<" << T << ", " << r << ", " << (vec2 ? "true" : "false") << ", " << (two ? 0 : 2)
+      << ">(S, args, lds_raw, Prog" << idx << "{}, blockIdx.x, gridDim.x);\n}\n";
     return o.str();
 }
 

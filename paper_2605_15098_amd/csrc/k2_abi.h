@@ -18,7 +18,12 @@ namespace svp {
 
 // Block-pass ops (device program).
 enum K2Kind {
-    K2_LAYOUT = 0,   // a: packed register local bits (5 bits each, ascending)
+    K2_LAYOUT = 0,   // a: packed local bit of each register slot (5 bits
+                     // each, slot 0 lowest; any order); b: how the block
+                     // moves through LDS: -1 whole; 0..31 in two halves by
+                     // that local bit, held by the same slot before and
+                     // after; 32 + x in two halves by local bit x, a
+                     // thread-id bit at the same position before and after
     K2_DENSE = 1,    // a: slot; b: control kind; c: control slot or bit code;
                      // v[0..7]: row-major 2x2 (re, im)
     K2_H = 2,        // as K2_DENSE, Hadamard
@@ -103,28 +108,44 @@ struct K2Args {
     // tier launches a pass on one chunk of outer blocks at a time.
     uint64_t base_or;
     int32_t nblk_bits;
-    int32_t pad_;
+    int32_t half_lds;          // 1: every re-layout is split, so LDS holds
+                               // half the block (2^(l-1) amplitudes)
 };
 
 // LDS of a block pass, in this order (16-byte aligned pieces): the block
-// (2^l amplitudes), nug block-uniform factors (double2), the lane/wave factor
-// table (tab_count amplitudes), nut UTerms, nug UGroups.
+// (2^l amplitudes, or 2^(l-1) when every re-layout goes in halves), nug
+// block-uniform factors (double2), the lane/wave factor table (tab_count
+// amplitudes), nut UTerms, nug UGroups.
 struct K2Lds {
     uint32_t ufac, tabs, uterm, ugrp, total;
 };
 #if defined(__HIPCC_RTC__) || defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 __host__ __device__
 #endif
-inline K2Lds k2_lds_layout(int l, int amp, int nug, int tab_count, int nut)
+inline K2Lds k2_lds_layout(int l, int amp, int nug, int tab_count, int nut, int half_lds)
 {
     auto up = [](uint32_t x) { return (x + 15u) & ~15u; };
     K2Lds o;
-    o.ufac = up((uint32_t)amp << l);
+    o.ufac = up(((uint32_t)amp << l) >> (half_lds ? 1 : 0));
     o.tabs = up(o.ufac + 16u * (uint32_t)nug);
     o.uterm = up(o.tabs + (uint32_t)amp * (uint32_t)tab_count);
     o.ugrp = up(o.uterm + 16u * (uint32_t)nut);
     o.total = up(o.ugrp + 8u * (uint32_t)nug);
     return o;
+}
+
+// Canonical layout of a block pass (its load and store): register slot 0
+// holds local bit 0 and slots 1..r-1 hold local bits l-r .. l-2, so the
+// thread id spreads over local bits 1 .. l-r-1 (lanes walk consecutive
+// memory) and the top local bit l-1. Keeping the top bit a thread-id bit
+// lets most re-layouts split the block by it into halves of whole waves. A
+// block of r bits is all registers.
+#if defined(__HIPCC_RTC__) || defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+__host__ __device__
+#endif
+constexpr int k2_canon_bit(int j, int l, int r)
+{
+    return j == 0 ? 0 : (l == r ? j : l - r - 1 + j);
 }
 
 // Batched passes (one persistent launch over many states). Instance i is

@@ -174,13 +174,39 @@ struct K2Ctx {
     const unsigned char *tabs;   // the pass's lane/wave factors in LDS (type C)
 };
 
+// Local index x with bit b taken out (the bits above it move down one).
+__device__ __forceinline__ uint32_t drop_bit(uint32_t x, int b)
+{
+    return (x & ((1u << b) - 1u)) | ((x >> (b + 1)) << b);
+}
+
 // Re-layout through LDS: the amplitudes leave registers in layout rb_old and
-// come back in layout rb_new (both ascending local-bit lists).
+// come back in layout rb_new (local bit of each register slot, any order).
+// With split < 0 the whole block passes through LDS at once. Otherwise the
+// block moves in two halves, local bit x = 0 then x = 1, each stored at its
+// local index with bit x taken out, so LDS holds 2^(l-1) amplitudes:
+//  - split = x < 32: slot s holds x in both layouts; round h writes and
+//    reads the registers whose slot-s bit is h (the first round's reads do
+//    not overwrite the registers the second round writes);
+//  - split = 32 + x: x is the thread-id bit p in both layouts; round h is
+//    done by the threads whose bit p is h (whole waves when p >= 6), all of
+//    their registers.
 template <int LOGR, typename C>
-__device__ __forceinline__ void k2_layout(C *a, K2Ctx &cx, const int *rb_old, const int *rb_new)
+__device__ __forceinline__ void k2_layout(C *a, K2Ctx &cx, const int *rb_old, const int *rb_new, int split)
 {
     constexpr int R = 1 << LOGR;
-    {
+    // the new thread local index: the thread-id bits spread over the
+    // non-register bits, zeros inserted at the register bits in ascending order
+    uint32_t rmask = 0;
+#pragma unroll
+    for (int j = 0; j < LOGR; ++j) rmask |= 1u << rb_new[j];
+    uint32_t tnew = cx.tid;
+#pragma unroll
+    for (int j = 0; j < LOGR; ++j) {
+        tnew = insert0_32(tnew, __builtin_ctz(rmask));
+        rmask &= rmask - 1u;
+    }
+    if (split < 0) {
         const uint32_t tsw = swz<C>(cx.tloc) * (uint32_t)sizeof(C);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -190,24 +216,87 @@ __device__ __forceinline__ void k2_layout(C *a, K2Ctx &cx, const int *rb_old, co
                 if ((k >> j) & 1) kp |= 1u << rb_old[j];
             *reinterpret_cast<C *>(cx.lds + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C)))) = a[k];
         }
-    }
-    lds_barrier();
-    uint32_t x = cx.tid;
-#pragma unroll
-    for (int j = 0; j < LOGR; ++j) x = insert0_32(x, rb_new[j]);  // zeros land on register bits
-    cx.tloc = x;
-    {
-        const uint32_t tsw = swz<C>(cx.tloc) * (uint32_t)sizeof(C);
+        lds_barrier();
+        cx.tloc = tnew;
+        const uint32_t tsn = swz<C>(cx.tloc) * (uint32_t)sizeof(C);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             uint32_t kp = 0;
 #pragma unroll
             for (int j = 0; j < LOGR; ++j)
                 if ((k >> j) & 1) kp |= 1u << rb_new[j];
-            a[k] = *reinterpret_cast<const C *>(cx.lds + (tsw ^ (swz<C>(kp) * (uint32_t)sizeof(C))));
+            a[k] = *reinterpret_cast<const C *>(cx.lds + (tsn ^ (swz<C>(kp) * (uint32_t)sizeof(C))));
         }
+        lds_barrier();
+        return;
     }
-    lds_barrier();
+    if (split >= 32) {
+        const int x = split - 32;
+        uint32_t om = 0;
+#pragma unroll
+        for (int j = 0; j < LOGR; ++j) om |= 1u << rb_old[j];
+        const int p = x - __builtin_popcount(om & ((1u << x) - 1u));
+        const uint32_t mine = (cx.tid >> p) & 1u;
+        const uint32_t tso = swz<C>(drop_bit(cx.tloc, x)) * (uint32_t)sizeof(C);
+        const uint32_t tsn = swz<C>(drop_bit(tnew, x)) * (uint32_t)sizeof(C);
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+            if (mine == h) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    uint32_t kp = 0;
+#pragma unroll
+                    for (int j = 0; j < LOGR; ++j)
+                        if ((k >> j) & 1) kp |= 1u << rb_old[j];
+                    *reinterpret_cast<C *>(cx.lds + (tso ^ (swz<C>(drop_bit(kp, x)) * (uint32_t)sizeof(C)))) = a[k];
+                }
+            }
+            lds_barrier();
+            if (mine == h) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    uint32_t kp = 0;
+#pragma unroll
+                    for (int j = 0; j < LOGR; ++j)
+                        if ((k >> j) & 1) kp |= 1u << rb_new[j];
+                    a[k] = *reinterpret_cast<const C *>(cx.lds + (tsn ^ (swz<C>(drop_bit(kp, x)) * (uint32_t)sizeof(C))));
+                }
+            }
+            lds_barrier();
+        }
+        cx.tloc = tnew;
+        return;
+    }
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < LOGR; ++j)
+        if (rb_old[j] == split) s = j;
+    const uint32_t tso = swz<C>(drop_bit(cx.tloc, split)) * (uint32_t)sizeof(C);
+    const uint32_t tsn = swz<C>(drop_bit(tnew, split)) * (uint32_t)sizeof(C);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (((k >> s) & 1) != h) continue;
+            uint32_t kp = 0;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if (j != s && ((k >> j) & 1)) kp |= 1u << rb_old[j];
+            *reinterpret_cast<C *>(cx.lds + (tso ^ (swz<C>(drop_bit(kp, split)) * (uint32_t)sizeof(C)))) = a[k];
+        }
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (((k >> s) & 1) != h) continue;
+            uint32_t kp = 0;
+#pragma unroll
+            for (int j = 0; j < LOGR; ++j)
+                if (j != s && ((k >> j) & 1)) kp |= 1u << rb_new[j];
+            a[k] = *reinterpret_cast<const C *>(cx.lds + (tsn ^ (swz<C>(drop_bit(kp, split)) * (uint32_t)sizeof(C))));
+        }
+        lds_barrier();
+    }
+    cx.tloc = tnew;
 }
 
 // ---- dense window through the matrix cores (16x16x4 MFMA)
@@ -506,19 +595,22 @@ __device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t
 // args.bits[i]; the other memory bits come from the block number. Each thread
 // holds R = 2^LOGR amplitudes in registers; register slot j stands for local
 // bit rb[j]; the remaining local bits, in ascending order, are the bits of
-// threadIdx. A program starts and ends in the canonical layout: slot 0 =
-// local bit 0, slots 1.. = the top LOGR-1 local bits, so lanes walk
-// consecutive memory and, for complex64, slots 0 and 1 form one 16-byte
-// access. lds is laid out by k2_lds_layout.
+// threadIdx. A program starts and ends in the canonical layout
+// (k2_canon_bit: slot 0 = local bit 0, slots 1.. = local bits l-r .. l-2),
+// so lanes walk consecutive memory and, for complex64, slots 0 and 1 form
+// one 16-byte access. lds is laid out by k2_lds_layout.
 //
 // V2 must equal args.vec2: a compile-time access width keeps one load path in
 // the loop, so the wait for the current block counts only its own loads and
 // the next block's prefetch stays in flight.
 //
-// ALWAYS_PREFETCH issues the next block's loads on every iteration (the last
-// re-reads the current block) so their count is the same on every path; a
-// work-group with few blocks (the batched passes) skips it instead.
-template <typename T, int LOGR, bool V2, bool ALWAYS_PREFETCH, class Prog>
+// PF = 2 issues the next block's loads on every iteration (the last re-reads
+// the current block) so their count is the same on every path; PF = 1 (a
+// work-group with few blocks, the batched passes) skips it after the last
+// block; PF = 0 does not prefetch: the next block is loaded after the store,
+// for passes that keep two work-groups on a CU (half the registers each) and
+// let one compute while the other waits.
+template <typename T, int LOGR, bool V2, int PF, class Prog>
 __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
                                         unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
 {
@@ -529,7 +621,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     const uint32_t tid = threadIdx.x;
     const uint64_t nblocks = 1ull << args.nblk_bits;
     constexpr bool vec2 = V2;
-    const svp::K2Lds L = svp::k2_lds_layout(l, (int)sizeof(C), args.nug, args.tab_count, args.nut);
+    const svp::K2Lds L = svp::k2_lds_layout(l, (int)sizeof(C), args.nug, args.tab_count, args.nut, args.half_lds);
     double2 *ufac = reinterpret_cast<double2 *>(lds + L.ufac);
     C *tabs = reinterpret_cast<C *>(lds + L.tabs);
     svp::UTerm *uterm = reinterpret_cast<svp::UTerm *>(lds + L.uterm);
@@ -540,13 +632,21 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     gmask = uniform64(gmask);
     const uint64_t base_or = uniform64(args.base_or);
 
-    // canonical-layout addressing, the same for every block
-    uint64_t tmem_local = 0;
-    for (int i = 0; i < tb; ++i) tmem_local |= (uint64_t)((tid >> i) & 1u) << args.bits[i + 1];
-    uint64_t roff[LOGR];
-    roff[0] = 1ull << args.bits[0];
+    // canonical-layout addressing, the same for every block: the thread-id
+    // bits go, in ascending order, to the local bits that are not register bits
+    uint32_t canon_regs = 0;
 #pragma unroll
-    for (int j = 1; j < LOGR; ++j) roff[j] = 1ull << args.bits[tb + j];
+    for (int j = 0; j < LOGR; ++j) canon_regs |= 1u << svp::k2_canon_bit(j, l, LOGR);
+    uint64_t tmem_local = 0;
+    for (int i = 0, c = 0; i < l; ++i) {
+        if ((canon_regs >> i) & 1u) continue;
+        tmem_local |= (uint64_t)((tid >> c) & 1u) << args.bits[i];
+        ++c;
+    }
+    // (read as wave-uniform values: they stay in scalar registers)
+    uint64_t roff[LOGR];
+#pragma unroll
+    for (int j = 0; j < LOGR; ++j) roff[j] = uniform64(1ull << args.bits[svp::k2_canon_bit(j, l, LOGR)]);
 
     uint64_t bid = first;
     if (bid >= nblocks) return;
@@ -564,7 +664,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         __syncthreads();
     }
     uint64_t base = uniform64(k2_deposit(bid, gmask) | base_or);
-    C a[R], b[R];
+    C a[R], b[PF ? R : 1];
     k2_load<LOGR>(a, S, base | tmem_local, roff, vec2);
 
     for (;;) {
@@ -573,7 +673,8 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         // With a path-independent count of loads in flight, the wait for
         // this block's data does not also wait for the prefetch.
         const uint64_t nbase = has_next ? uniform64(k2_deposit(next, gmask) | base_or) : base;
-        if (ALWAYS_PREFETCH || has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
+        if constexpr (PF > 0)
+            if (PF == 2 || has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
 
         // Block-uniform phase factors of the diagonal runs: each is
         // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in
@@ -597,15 +698,30 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         // would pin dozens of registers and halve the resident work-groups.
         uint32_t tid_b = tid;
         asm volatile("" : "+v"(tid_b));
-        K2Ctx cx{tid_b, base, tid_b << 1, lds, ufac, args.table, reinterpret_cast<const unsigned char *>(tabs)};
+        // canonical local index of the thread: tid bits 0 .. tb-2 on local
+        // bits 1 .. tb-1, the top tid bit on local bit l-1
+        const uint32_t tloc0 = tb == 0 ? 0u
+                                       : ((tid_b & ((1u << (tb - 1)) - 1u)) << 1) |
+                                             (((tid_b >> (tb - 1)) & 1u) << (l - 1));
+        K2Ctx cx{tid_b, base, tloc0, lds, ufac, args.table, reinterpret_cast<const unsigned char *>(tabs)};
         prog.template run<T, LOGR>(a, cx);
 
-        // the program ends in the canonical layout
-        k2_store<LOGR>(a, S, base | tmem_local, roff, vec2);
+        // the program ends in the canonical layout. The thread's address bits
+        // are laundered so that the store recomputes its addresses instead of
+        // keeping the load's live across the program (dozens of registers).
+        uint64_t tm_st = tmem_local;
+        asm volatile("" : "+v"(tm_st));
+        k2_store<LOGR>(a, S, base | tm_st, roff, vec2);
         if (!has_next) break;
         if (args.nug > 0) lds_barrier();  // the next block's factors overwrite ufac
+        if constexpr (PF > 0) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) a[k] = b[k];
+            for (int k = 0; k < R; ++k) a[k] = b[k];
+        } else {
+            uint64_t tm_ld = tmem_local;
+            asm volatile("" : "+v"(tm_ld));
+            k2_load<LOGR>(a, S, nbase | tm_ld, roff, vec2);
+        }
         base = nbase;
         bid = next;
     }
@@ -616,8 +732,8 @@ template <typename T, int LOGR, class Prog>
 __device__ __forceinline__ void k2_body_any(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
                                             unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
 {
-    if (args.vec2) k2_body<T, LOGR, true, false>(S, args, lds, prog, first, stride);
-    else k2_body<T, LOGR, false, false>(S, args, lds, prog, first, stride);
+    if (args.vec2) k2_body<T, LOGR, true, 1>(S, args, lds, prog, first, stride);
+    else k2_body<T, LOGR, false, 1>(S, args, lds, prog, first, stride);
 }
 
 // ------------------------------------------------------------ interpreter
@@ -639,7 +755,7 @@ struct K2Interp {
         int rb[LOGR];
         rb[0] = 0;
 #pragma unroll
-        for (int j = 1; j < LOGR; ++j) rb[j] = l - LOGR + j;
+        for (int j = 1; j < LOGR; ++j) rb[j] = svp::k2_canon_bit(j, l, LOGR);
         for (int oi = 0; oi < nops; ++oi) {
             const svp::K2Op &op = ops[oi];
             const int kind = op.kind;
@@ -658,7 +774,7 @@ struct K2Interp {
                 int nrb[LOGR];
 #pragma unroll
                 for (int j = 0; j < LOGR; ++j) nrb[j] = (op.a >> (5 * j)) & 31;
-                k2_layout<LOGR>(a, cx, rb, nrb);
+                k2_layout<LOGR>(a, cx, rb, nrb, op.b);
 #pragma unroll
                 for (int j = 0; j < LOGR; ++j) rb[j] = nrb[j];
             } else if (kind == svp::K2_MFMA) {

@@ -298,7 +298,7 @@ template <typename T, int LOGR, bool MFMA>
 static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hipStream_t st)
 {
     using C = typename CT<T>::type;
-    const size_t lds = svp::k2_lds_layout(a.l, (int)sizeof(C), a.nug, a.tab_count, a.nut).total;
+    const size_t lds = svp::k2_lds_layout(a.l, (int)sizeof(C), a.nug, a.tab_count, a.nut, a.half_lds).total;
     static size_t attr_bytes = 64 * 1024;
     if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k2_kernel<T, LOGR, MFMA>,

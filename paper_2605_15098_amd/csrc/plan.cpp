@@ -339,24 +339,35 @@ struct Builder {
 
     // LDS of one work-group on gfx950.
     static constexpr uint32_t kLdsLimit = 160 * 1024;
+    // blocks above this many bytes stage half at a time (one 2^14 complex64
+    // block would otherwise take 128 KiB of the CU's 160 KiB)
+    static constexpr size_t kHalfFrom = 64 * 1024;
 
-    // A block pass whose factor tables would not fit in LDS next to the
-    // block is compiled again with one op per diagonal gate (no tables).
+    // A pass is compiled with lane/wave factor tables and split re-layouts
+    // when it can be; a pass whose LDS would overflow drops the tables (one
+    // op per diagonal gate), and one whose re-layouts cannot all be split
+    // stages the whole block.
     void compile_block(const std::vector<MGate> &q, const std::vector<int> &B)
     {
         const size_t ops0 = plan.ops.size(), tab0 = plan.table.size(), steps0 = plan.steps.size();
         const PlanStats st0 = plan.stats;
-        compile_block_impl(q, B, true);
-        const Step &s = plan.steps.back();
-        if (k2_lds_layout(s.l, ab, s.nug, s.tab_count, s.nut).total <= kLdsLimit) return;
-        plan.ops.resize(ops0);
-        plan.table.resize(tab0);
-        plan.steps.resize(steps0);
-        plan.stats = st0;
-        compile_block_impl(q, B, false);
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            const bool tables = attempt < 2, allow_half = (attempt & 1) == 0;
+            const bool split_ok = compile_block_impl(q, B, tables, allow_half);
+            const Step &s = plan.steps.back();
+            if (attempt == 3 ||
+                (split_ok && k2_lds_layout(s.l, ab, s.nug, s.tab_count, s.nut, s.half_lds).total <= kLdsLimit))
+                return;
+            plan.ops.resize(ops0);
+            plan.table.resize(tab0);
+            plan.steps.resize(steps0);
+            plan.stats = st0;
+        }
     }
 
-    void compile_block_impl(const std::vector<MGate> &q, const std::vector<int> &B, bool tables)
+    // Returns false when the pass was to stage half the block but a
+    // re-layout had no slot that keeps its bit.
+    bool compile_block_impl(const std::vector<MGate> &q, const std::vector<int> &B, bool tables, bool allow_half)
     {
         const int r = logr;
         const bool combine = cfg.fuse_k >= 1;
@@ -365,10 +376,9 @@ struct Builder {
         std::vector<int> rank(64, -1);
         for (int i = 0; i < (int)B.size(); ++i) rank[B[i]] = i;
         // canonical layout (load and store): slot 0 = local bit 0, the other
-        // slots = the top local bits
+        // slots = the local bits below the top one
         std::vector<int> canon(r);
-        canon[0] = 0;
-        for (int j = 1; j < r; ++j) canon[j] = l - r + j;
+        for (int j = 0; j < r; ++j) canon[j] = k2_canon_bit(j, l, r);
         std::vector<int> rb = canon;  // register slot j holds local bit rb[j]
         std::vector<UGroup> ugroups;
         std::vector<UTerm> uterms;
@@ -377,16 +387,101 @@ struct Builder {
                 if (rb[j] == local) return j;
             return -1;
         };
-        auto emit_layout = [&](std::vector<int> nrb) {
-            std::sort(nrb.begin(), nrb.end());
-            if (nrb == rb) return;
+        // Split re-layouts (half): the block moves through LDS in two halves,
+        // so LDS holds 2^(l-1) amplitudes and two work-groups fit on a CU.
+        // The halves are split by a local bit that one register slot holds
+        // before and after, or by a local bit that is the same thread-id bit
+        // before and after (a wave bit, so each half is whole waves). Slot
+        // order is free: a kept bit stays in its slot and a new canonical bit
+        // goes to its canonical slot when that is free (so the return to the
+        // canonical layout usually shares a slot); when no split exists a
+        // layout keeps one current bit.
+        bool half = false, split_ok = true;
+        auto canon_slot = [&](int b) {
+            for (int j = 0; j < r; ++j)
+                if (canon[j] == b) return j;
+            return -1;
+        };
+        auto push_layout = [&](const std::vector<int> &nrb, int split) {
             K2Op op{};
             op.kind = K2_LAYOUT;
             int packed = 0;
             for (int j = 0; j < r; ++j) packed |= nrb[j] << (5 * j);
             op.a = packed;
+            op.b = split;
             plan.ops.push_back(op);
             rb = nrb;
+        };
+        // the split code of a re-layout rb -> nrb (K2_LAYOUT's b), -1 if none
+        auto split_of = [&](const std::vector<int> &nrb) {
+            for (int j = 0; j < r; ++j)
+                if (nrb[j] == rb[j]) return rb[j];
+            uint32_t om = 0, nm = 0;
+            for (int j = 0; j < r; ++j) {
+                om |= 1u << rb[j];
+                nm |= 1u << nrb[j];
+            }
+            for (int x = l - 1; x >= 0; --x) {
+                if (((om | nm) >> x) & 1u) continue;
+                const uint32_t below = (1u << x) - 1u;
+                const int po = x - __builtin_popcount(om & below), pn = x - __builtin_popcount(nm & below);
+                // a lane bit splits within waves: only blocks of one wave or less
+                if (po == pn && (po >= 6 || l - r <= 6)) return 32 + x;
+            }
+            return -1;
+        };
+        auto emit_split = [&](const std::vector<int> &nrb) {
+            if (nrb == rb) return;
+            const int sb = half ? split_of(nrb) : -1;
+            if (half && sb < 0) split_ok = false;
+            push_layout(nrb, sb);
+        };
+        // a layout in exactly this slot order (the canonical one); without a
+        // split one of its bits is brought in first, in its slot
+        auto emit_fixed = [&](const std::vector<int> &nrb) {
+            if (half && nrb != rb && split_of(nrb) < 0) {
+                for (int j = 0; j < r; ++j)
+                    if (std::find(rb.begin(), rb.end(), nrb[j]) == rb.end()) {
+                        std::vector<int> mid = rb;
+                        mid[j] = nrb[j];
+                        emit_split(mid);
+                        break;
+                    }
+            }
+            emit_split(nrb);
+        };
+        auto arrange = [&](const std::vector<int> &S) {
+            std::vector<int> nrb(r, -1), rest;
+            for (int b : S)
+                if (slot_of(b) >= 0) nrb[slot_of(b)] = b;
+            for (int b : S) {
+                if (slot_of(b) >= 0) continue;
+                const int j = canon_slot(b);
+                if (j >= 0 && nrb[j] < 0) nrb[j] = b;
+                else rest.push_back(b);
+            }
+            std::sort(rest.begin(), rest.end());
+            size_t ri = 0;
+            for (int j = 0; j < r; ++j)
+                if (nrb[j] < 0) nrb[j] = rest[ri++];
+            return nrb;
+        };
+        // a layout holding the bits S (in priority order), slots arranged
+        auto emit_layout = [&](std::vector<int> S) {
+            std::vector<int> nrb = arrange(S);
+            if (half && nrb != rb && split_of(nrb) < 0) {
+                bool keeps = false;
+                for (int b : S) keeps = keeps || slot_of(b) >= 0;
+                if (!keeps) {
+                    // keep a canonical bit if one is held, else slot 0's bit
+                    int keep = rb[0];
+                    for (int j = r - 1; j >= 0; --j)
+                        if (canon_slot(rb[j]) >= 0) keep = rb[j];
+                    S.back() = keep;
+                    nrb = arrange(S);
+                }
+            }
+            emit_split(nrb);
         };
         // a non-register bit as the kernel tests it: local bit index, or
         // 64 + memory bit for a bit of the block base
@@ -482,6 +577,9 @@ struct Builder {
                 i = e;
             }
         }
+        // matrix-core windows read the whole block from LDS
+        half = allow_half && r >= 2 && (cfg.half_lds == 2 || (cfg.half_lds == 1 && ((size_t)ab << l) > kHalfFrom)) &&
+               std::find_if(wend.begin(), wend.end(), [](int e) { return e > 0; }) == wend.end();
         auto emit_mfma = [&](size_t i0, size_t i1, uint32_t m) {
             std::vector<int> wl;
             for (int b = 0; b < l; ++b)
@@ -609,11 +707,12 @@ struct Builder {
             op.v[0] = std::ldexp(1.0, -(hscale / 2)) * ((hscale & 1) ? 0.70710678118654752440 : 1.0);
             plan.ops.push_back(op);
         }
-        emit_layout(canon);
+        emit_fixed(canon);
         Step s;
         s.kind = ST_K2;
         s.l = l;
         s.logr = r;
+        s.half_lds = half ? 1 : 0;
         for (int i = 0; i < l; ++i) s.bits[i] = B[i];
         s.op_begin = begin;
         s.op_count = (int)plan.ops.size() - begin;
@@ -632,6 +731,7 @@ struct Builder {
         plan.stats.phases += 1;
         plan.stats.passes += 1;
         plan.stats.bytes += 2.0 * state_bytes;
+        return split_ok;
     }
 };
 

@@ -65,6 +65,7 @@ struct Step {
     int ug_off = 0, nug = 0;  // ST_K2: block-uniform factor groups
     int tab_off = 0, tab_count = 0;  // ST_K2: lane/wave factor table (complex doubles)
     int ut_off = 0, nut = 0;         // ST_K2: UTerm array of the block-uniform groups
+    int half_lds = 0;                // ST_K2: every re-layout split (LDS holds half the block)
     int p = 0, v = 0;       // ST_K3
     int ngates = 0;         // gates applied by this step
 };
@@ -81,6 +82,8 @@ struct PlanConfig {
     int pin_low = -1;         // low memory bits kept in every block (-1 = auto)
     int fuse_k = 1;           // 0: one op per gate; 1: diagonal runs combined,
                               // Hadamard normalization deferred
+    int half_lds = 1;         // re-layouts in two halves: 0 never, 1 for blocks
+                              // above 64 KiB, 2 whenever possible
 };
 
 struct PlanStats {

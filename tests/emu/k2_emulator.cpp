@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <cstdlib>
 #include <vector>
 
 #include "../../paper_2605_15098_amd/csrc/jit.h"
@@ -76,7 +77,7 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
         std::vector<std::vector<cd>> a(NT, std::vector<cd>(R));
         std::vector<int> rb(r);
         rb[0] = 0;
-        for (int j = 1; j < r; ++j) rb[j] = tb + j;
+        for (int j = 1; j < r; ++j) rb[j] = k2_canon_bit(j, l, r);
         std::vector<uint32_t> tloc(NT);
         auto set_layout = [&]() {
             uint32_t rmask = 0;
@@ -118,7 +119,95 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
             for (int k = 0; k < R; ++k) a[tid][k] = S[amp_mem(tid, k)];
         for (int oi = 0; oi < st.op_count; ++oi) {
             const K2Op &op = plan.ops[st.op_begin + oi];
-            if (op.kind == K2_LAYOUT) {
+            if (op.kind == K2_LAYOUT && op.b >= 32) {
+                // split by a thread-id bit: round h is done by the threads
+                // whose id bit p is h, all their registers, through half the LDS
+                const int x = op.b - 32;
+                std::vector<int> nrb(r);
+                uint32_t om = 0, nm = 0;
+                for (int j = 0; j < r; ++j) {
+                    nrb[j] = (op.a >> (5 * j)) & 31;
+                    om |= 1u << rb[j];
+                    nm |= 1u << nrb[j];
+                }
+                const uint32_t below = (1u << x) - 1u;
+                const int p = x - __builtin_popcount(om & below);
+                if (((om | nm) >> x) & 1u || p != x - __builtin_popcount(nm & below)) {
+                    return_error = true;
+                    return;
+                }
+                auto drop = [](uint32_t v, int b) { return (v & ((1u << b) - 1u)) | ((v >> (b + 1)) << b); };
+                std::vector<uint32_t> old_loc(NT * R);
+                for (int tid = 0; tid < NT; ++tid)
+                    for (int k = 0; k < R; ++k) old_loc[tid * R + k] = amp_loc(tid, k);
+                rb = nrb;
+                set_layout();
+                std::vector<cd> half(1ull << (l - 1));
+                for (int h = 0; h < 2; ++h) {
+                    std::vector<int> filled(half.size(), 0);
+                    for (int tid = 0; tid < NT; ++tid) {
+                        if (((tid >> p) & 1) != h) continue;
+                        for (int k = 0; k < R; ++k) {
+                            const uint32_t i = drop(old_loc[tid * R + k], x);
+                            if (i >= half.size() || filled[i]++) return_error = true;
+                            else half[i] = a[tid][k];
+                        }
+                    }
+                    for (int tid = 0; tid < NT; ++tid) {
+                        if (((tid >> p) & 1) != h) continue;
+                        for (int k = 0; k < R; ++k) {
+                            const uint32_t i = drop(amp_loc(tid, k), x);
+                            if (i >= half.size() || filled[i]-- != 1) return_error = true;
+                            else a[tid][k] = half[i];
+                        }
+                    }
+                }
+            } else if (op.kind == K2_LAYOUT && op.b >= 0) {
+                // split re-layout: two rounds through half the LDS, as the
+                // kernel does it (bit op.b taken out of the local index);
+                // every cell of a round is written once and read once
+                const int sb = op.b;
+                std::vector<int> nrb(r);
+                for (int j = 0; j < r; ++j) nrb[j] = (op.a >> (5 * j)) & 31;
+                int s = -1;
+                for (int j = 0; j < r; ++j)
+                    if (rb[j] == sb && nrb[j] == sb) s = j;
+                if (s < 0) {
+                    return_error = true;
+                    return;
+                }
+                auto drop = [](uint32_t x, int b) { return (x & ((1u << b) - 1u)) | ((x >> (b + 1)) << b); };
+                const std::vector<int> old_rb = rb;
+                const std::vector<uint32_t> old_tloc = tloc;
+                rb = nrb;
+                set_layout();
+                const std::vector<uint32_t> new_tloc = tloc;
+                std::vector<cd> half(1ull << (l - 1));
+                for (int h = 0; h < 2; ++h) {
+                    std::vector<int> filled(half.size(), 0);
+                    for (int tid = 0; tid < NT; ++tid)
+                        for (int k = 0; k < R; ++k) {
+                            if (((k >> s) & 1) != h) continue;
+                            uint32_t x = old_tloc[tid];
+                            for (int j = 0; j < r; ++j)
+                                if (j != s && ((k >> j) & 1)) x |= 1u << old_rb[j];
+                            const uint32_t i = drop(x, sb);
+                            if (i >= half.size() || filled[i]++) return_error = true;
+                            else half[i] = a[tid][k];
+                        }
+                    for (int tid = 0; tid < NT; ++tid)
+                        for (int k = 0; k < R; ++k) {
+                            if (((k >> s) & 1) != h) continue;
+                            uint32_t x = new_tloc[tid];
+                            for (int j = 0; j < r; ++j)
+                                if (j != s && ((k >> j) & 1)) x |= 1u << nrb[j];
+                            const uint32_t i = drop(x, sb);
+                            if (i >= half.size() || filled[i]-- != 1) return_error = true;
+                            else a[tid][k] = half[i];
+                        }
+                }
+            } else if (op.kind == K2_LAYOUT) {
+                if (st.half_lds) return_error = true;  // LDS holds only half the block
                 for (int tid = 0; tid < NT; ++tid)
                     for (int k = 0; k < R; ++k) lds[amp_loc(tid, k)] = a[tid][k];
                 for (int j = 0; j < r; ++j) rb[j] = (op.a >> (5 * j)) & 31;
@@ -179,6 +268,7 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
                 for (int tid = 0; tid < NT; ++tid)
                     for (int k = 0; k < R; ++k) a[tid][k] *= op.v[0];
             } else if (op.kind == K2_MFMA) {
+                if (st.half_lds) return_error = true;  // windows read the whole block from LDS
                 // unpack the operand-ordered real matrix and apply it to every
                 // vector of the window bits, in FP64
                 const int K = op.b, W = 1 << K, D = 2 * W, steps = D / 4;
@@ -266,6 +356,7 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
 {
     PlanConfig c;
     g_dtype = dtype;
+    if (const char *e = std::getenv("SV_HALF_LDS")) c.half_lds = std::atoi(e);
     c.n = n;
     c.dtype = dtype;
     c.mode = mode;
@@ -310,6 +401,8 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
     counts_out[1] = plan.stats.swaps;
     counts_out[2] = (int64_t)plan.ops.size();
     counts_out[3] = (int64_t)plan.table.size();
+    counts_out[4] = 0;  // block passes that stage half the block
+    for (const Step &st : plan.steps) counts_out[4] += st.kind == ST_K2 && st.half_lds;
     return 0;
 }
 
@@ -320,6 +413,7 @@ extern "C" int emu_jit_check(int n, int dtype, int l, int logr, int policy, int 
                              const void *gates, size_t m, char *log_out, size_t log_cap)
 {
     PlanConfig c;
+    if (const char *e = std::getenv("SV_HALF_LDS")) c.half_lds = std::atoi(e);
     c.n = n;
     c.dtype = dtype;
     c.mode = 1;

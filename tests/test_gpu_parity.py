@@ -250,3 +250,26 @@ def test_compiled_passes_match_interpreter_bitwise(dtype, monkeypatch):
         for i in range(2):
             assert np.array_equal(outs[i].view(np.uint8), outs[i + 2].view(np.uint8))
             assert np.max(np.abs(outs[i] - want)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_split_relayouts_match_oracle_and_interpreter(dtype, monkeypatch):
+    """Re-layouts through half the LDS (forced at every block size): the
+    compiled and interpreted passes agree bit for bit and match the oracle,
+    with and without the dependence-graph order."""
+    monkeypatch.setenv("SV_HALF_LDS", "2")
+    rng = np.random.default_rng(41)
+    lmax = 14 if dtype == "c64" else 13
+    for n, l, reg in ((8, 5, 2), (11, 8, 3), (13, 10, 4), (15, lmax, 5 if dtype == "c64" else 4)):
+        g = np.concatenate([W.random_mixed_circuit(n, 120, rng), W.qpe_gates(n, 0.37)])
+        init = rand_state(n, rng)
+        want = oracle.apply(n, g, init)
+        for pol in ("graph", "lookahead"):
+            outs = []
+            for jit in ("0", "1"):
+                monkeypatch.setenv("SV_JIT", jit)
+                log(f"case split jit={jit} n={n} l={l} reg={reg} policy={pol} dtype={dtype}")
+                got, _, _ = run(n, dtype, g, sv.schedule(block_qubits=l, reg_qubits=reg, swap_policy=pol), init)
+                outs.append(got)
+            assert np.array_equal(outs[0].view(np.uint8), outs[1].view(np.uint8))
+            assert np.max(np.abs(outs[0] - want)) <= TOL[dtype]

@@ -56,7 +56,7 @@ def emu():
 def run(n, gates, state=None, dtype=0, mode=1, l=0, logr=4, policy=1, remap=0, diag_free=1,
         pin=-1, fuse=1):
     s = oracle.zero_state(n) if state is None else np.array(state, dtype=np.complex128)
-    counts = (ctypes.c_int64 * 4)()
+    counts = (ctypes.c_int64 * 5)()
     g = np.ascontiguousarray(gates)
     rc = emu().emu_apply(n, dtype, mode, l, logr, policy, remap, diag_free, pin, fuse,
                          g.ctypes.data if len(g) else None, len(g),
@@ -237,3 +237,45 @@ def test_graph_schedule_moves_gates_only_across_commuting_ones():
     for cfg in (dict(l=4, logr=2, pin=1), dict(l=6, logr=3), dict(l=5, logr=2, fuse=0), dict(l=8, logr=4, pin=3)):
         got, _ = run(n, g, psi0, policy=2, **cfg)
         assert np.max(np.abs(got - want)) < 1e-12, cfg
+
+
+HALF = [dict(), dict(policy=1), dict(logr=2), dict(logr=3, pin=0), dict(fuse=0), dict(diag_free=0)]
+
+
+@pytest.mark.parametrize("cfg", HALF, ids=lambda c: ",".join(f"{k}={v}" for k, v in c.items()) or "default")
+@pytest.mark.parametrize("n,l", [(6, 3), (9, 6), (11, 8), (12, 10)])
+def test_split_relayout_programs(n, l, cfg, monkeypatch):
+    """Every re-layout moves the block through half the LDS (forced at any
+    block size): the emulator runs both rounds with the kernel's index map and
+    flags a cell written twice, read unwritten or out of range."""
+    if cfg.get("logr", 4) > l:
+        pytest.skip("fewer local bits than register bits")
+    monkeypatch.setenv("SV_HALF_LDS", "2")
+    rng = np.random.default_rng(n * 31 + l)
+    g = W.random_mixed_circuit(n, 120, rng)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    got, counts = run(n, g, psi0, l=l, **cfg)
+    assert np.max(np.abs(got - oracle.apply(n, g, psi0))) < 1e-12
+    assert counts[4] == counts[0]  # every pass split
+    phi = W.phi_for_seed(n)
+    got, counts = run(n, W.qpe_gates(n, phi), l=l, **cfg)
+    assert np.max(np.abs(got - cf.qpe_state(n, phi))) < 1e-12
+    assert counts[4] == counts[0]
+
+
+@pytest.mark.parametrize("dtype,l", [(0, 14), (1, 13)])
+def test_split_relayout_default_sizes(dtype, l):
+    """At the default block sizes (2^14 complex64, 2^13 complex128 = 128 KiB)
+    every pass stages half the block."""
+    n = l + 2
+    rng = np.random.default_rng(l)
+    g = W.random_mixed_circuit(n, 150, rng)
+    want = oracle.apply(n, g)
+    got, counts = run(n, g, dtype=dtype, l=l, logr=5 if dtype == 0 else 4)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert counts[4] == counts[0] > 0
+    phi = W.phi_for_seed(n)
+    got, counts = run(n, W.qpe_gates(n, phi), dtype=dtype, l=l, logr=5 if dtype == 0 else 4)
+    assert np.max(np.abs(got - cf.qpe_state(n, phi))) < 1e-12
+    assert counts[4] == counts[0] > 0
