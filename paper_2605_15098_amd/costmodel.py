@@ -252,7 +252,11 @@ def evaluate(idxs: Sequence[int], model_path: str, dtype: str = "c64", repeats: 
         learned_tune_s = time.perf_counter() - t1
         li = [_fields(c) for c in cands].index(_fields(pick))
         try:
-            ms, _ = sv.sv_tune_time(st.h, g, cands, repeats)
+            # one candidate per call, each logged: a large state times for minutes
+            ms = []
+            for j, c in enumerate(cands):
+                ms += sv.sv_tune_time(st.h, g, [c], repeats)[0]
+                log(f"eval {i} n={n}: candidate {j + 1}/{ncand} {ms[-1]:.1f} ms")
             pms, _ = sv.sv_tune_time(st.h, g, [sv.paper_schedule(paper_l)], repeats)
         except sv.SvError as e:
             st.close()
