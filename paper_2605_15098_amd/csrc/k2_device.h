@@ -195,6 +195,10 @@ template <int LOGR, typename C>
 __device__ __forceinline__ void k2_layout(C *a, K2Ctx &cx, const int *rb_old, const int *rb_new, int split)
 {
     constexpr int R = 1 << LOGR;
+    // The thread's indices are laundered here so that each re-layout derives
+    // its LDS addresses when it runs, instead of the program computing every
+    // re-layout's addresses at the start of the block and holding them.
+    asm volatile("" : "+v"(cx.tid), "+v"(cx.tloc));
     // the new thread local index: the thread-id bits spread over the
     // non-register bits, zeros inserted at the register bits in ascending order
     uint32_t rmask = 0;
@@ -621,11 +625,12 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     const uint32_t tid = threadIdx.x;
     const uint64_t nblocks = 1ull << args.nblk_bits;
     constexpr bool vec2 = V2;
+    // (offsets read as wave-uniform values: they stay in scalar registers)
     const svp::K2Lds L = svp::k2_lds_layout(l, (int)sizeof(C), args.nug, args.tab_count, args.nut, args.half_lds);
-    double2 *ufac = reinterpret_cast<double2 *>(lds + L.ufac);
-    C *tabs = reinterpret_cast<C *>(lds + L.tabs);
-    svp::UTerm *uterm = reinterpret_cast<svp::UTerm *>(lds + L.uterm);
-    svp::UGroup *ugrp = reinterpret_cast<svp::UGroup *>(lds + L.ugrp);
+    double2 *ufac = reinterpret_cast<double2 *>(lds + __builtin_amdgcn_readfirstlane(L.ufac));
+    C *tabs = reinterpret_cast<C *>(lds + __builtin_amdgcn_readfirstlane(L.tabs));
+    svp::UTerm *uterm = reinterpret_cast<svp::UTerm *>(lds + __builtin_amdgcn_readfirstlane(L.uterm));
+    svp::UGroup *ugrp = reinterpret_cast<svp::UGroup *>(lds + __builtin_amdgcn_readfirstlane(L.ugrp));
     // memory bits outside the block, as a mask (the block number is deposited there)
     uint64_t gmask = 0;
     for (int i = 0; i < args.nblk_bits; ++i) gmask |= 1ull << args.nbits[i];
