@@ -32,6 +32,18 @@
  * borrowed for the duration of a call. Output pointers may be host or device
  * memory (detected with hipPointerGetAttributes): host outputs synchronize the
  * handle's stream, device outputs are stream-ordered.
+ *
+ * Environment (read when a circuit is planned or a pass is compiled; none is
+ * needed in normal use):
+ *   SV_JIT=0            run block passes through the op interpreter instead
+ *                       of kernels compiled for each pass (same bits)
+ *   SV_JIT_CACHE_DIR    directory of compiled pass modules kept across runs
+ *   SV_PIN_BITS, SV_LOGR  override the schedule's pinned low qubits and
+ *                       register qubits per thread (tuning experiments)
+ *   SV_HALF_LDS         0: re-lay blocks out through LDS whole; 1 (default):
+ *                       in two halves for blocks above 64 KiB; 2: in halves
+ *                       whenever possible (tests)
+ *   SV_TRACE_HOST       print host-side upload and launch timings to stderr
  */
 #ifndef SVMI_SV_H_INCLUDED
 #define SVMI_SV_H_INCLUDED

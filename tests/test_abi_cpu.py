@@ -215,6 +215,27 @@ def test_schedule_field_validation():
         sv.sv_plan(8, "c128", g, sv.schedule(reg_qubits=5))
     assert e.value.status == sv.SV_ERR_UNSUPPORTED
     assert sv.sv_plan(8, "c64", g, sv.schedule(reg_qubits=5))["passes"] >= 1
+    # the dependence-graph order needs virtual remap; unknown policies are rejected
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(8, "c64", g, sv.schedule(swap_policy="graph", remap="explicit"))
+    assert e.value.status == sv.SV_ERR_UNSUPPORTED
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_plan(8, "c64", g, sv.schedule(swap_policy=3))
+    assert e.value.status == sv.SV_ERR_INVALID_ARG
+    assert sv.sv_plan(8, "c64", g, sv.schedule("plain", swap_policy="graph"))["passes"] == W.qpe_gate_count(8)[0]
+
+
+def test_graph_schedule_counts():
+    """The dependence-graph order applies every gate once and, on these
+    circuits, never takes more block passes than list order (the states it
+    produces are checked against the oracle in the emulator and GPU tests)."""
+    rng = np.random.default_rng(19)
+    for n, l in ((12, 8), (16, 10), (20, 13)):
+        for g in (W.qpe_gates(n, 0.3), W.random_mixed_circuit(n, 200, rng)):
+            a = sv.sv_plan(n, "c64", g, sv.schedule(block_qubits=l, swap_policy="lookahead"))
+            b = sv.sv_plan(n, "c64", g, sv.schedule(block_qubits=l))
+            assert a["gates"] == b["gates"]
+            assert b["passes"] <= a["passes"]
 
 
 def test_precompile_without_device():
