@@ -279,3 +279,23 @@ def test_split_relayout_default_sizes(dtype, l):
     got, counts = run(n, W.qpe_gates(n, phi), dtype=dtype, l=l, logr=5 if dtype == 0 else 4)
     assert np.max(np.abs(got - cf.qpe_state(n, phi))) < 1e-12
     assert counts[4] == counts[0] > 0
+
+
+@pytest.mark.parametrize("half", ["0", "2"])
+@pytest.mark.parametrize("n,l,logr,pin", [(1, 1, 1, 0), (2, 2, 1, 0), (3, 2, 1, 1), (5, 5, 4, 0), (6, 3, 2, 2),
+                                          (8, 4, 2, 3), (10, 6, 3, 5)])
+def test_graph_schedule_edge_cases(n, l, logr, pin, half, monkeypatch):
+    """Degenerate shapes for the dependence-graph order, with whole and
+    split re-layouts: one-qubit states, the whole state in one block, all but
+    one local qubit pinned, circuits of diagonal gates only and of gates on
+    pinned qubits only."""
+    monkeypatch.setenv("SV_HALF_LDS", half)
+    rng = np.random.default_rng(n * 7 + l)
+    circuits = [W.random_mixed_circuit(n, 60, rng),
+                W.gates_from_tuples([("P", int(rng.integers(n)), -1, float(rng.random() * 6)) for _ in range(30)]),
+                W.gates_from_tuples([("H", int(rng.integers(max(1, pin))), -1, 0.0) for _ in range(20)])]
+    for g in circuits:
+        psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+        psi0 /= np.linalg.norm(psi0)
+        got, _ = run(n, g, psi0, l=l, logr=logr, policy=2, pin=pin)
+        assert np.max(np.abs(got - oracle.apply(n, g, psi0))) < 1e-12
