@@ -623,6 +623,11 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     const int l = args.l;
     const int tb = l - LOGR;
     const uint32_t tid = threadIdx.x;
+    // The wave number is wave-uniform (a scalar register) and the lane comes
+    // back from two lane-count instructions, so the thread index is rebuilt
+    // per block instead of being held in a vector register (or spilled) for
+    // the whole launch.
+    const uint32_t wave_no = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t nblocks = 1ull << args.nblk_bits;
     constexpr bool vec2 = V2;
     // (offsets read as wave-uniform values: they stay in scalar registers)
@@ -685,7 +690,8 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in
         // 64-bit fixed-point turns and evaluated once per block.
         if (args.nug > 0) {
-            for (int g = threadIdx.x; g < args.nug; g += blockDim.x) {
+            const int gtid = (int)((wave_no << 6) | __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
+            for (int g = gtid; g < args.nug; g += blockDim.x) {
                 const svp::UTerm *tm = uterm + ugrp[g].term_off;
                 uint64_t acc = 0;
                 for (int j = 0; j < ugrp[g].nterms; ++j)
@@ -701,7 +707,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         // addresses and per-thread table factors are recomputed for each
         // block instead of being hoisted out of the block loop, where they
         // would pin dozens of registers and halve the resident work-groups.
-        uint32_t tid_b = tid;
+        uint32_t tid_b = (wave_no << 6) | __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
         asm volatile("" : "+v"(tid_b));
         // canonical local index of the thread: tid bits 0 .. tb-2 on local
         // bits 1 .. tb-1, the top tid bit on local bit l-1
