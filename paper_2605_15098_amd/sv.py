@@ -66,6 +66,10 @@ class sv_stats(ctypes.Structure):
 
 def schedule(mode="partitioned", block_qubits=0, outer_qubits=0, fuse_k=1, swap_policy="graph",
              remap="virtual", diag_free=True, tuner="none", reg_qubits=0, pin_qubits=0) -> sv_schedule:
+    """An sv_schedule (see include/sv.h for every field). swap_policy: "graph"
+    (default; gates in any order their dependences allow), "lookahead" (list
+    order, look-ahead gathering) or "lru" (list order, the paper's victim).
+    Zero for block_qubits, reg_qubits or pin_qubits means the dtype's default."""
     s = sv_schedule()
     s.mode = {"plain": SV_PLAIN, "partitioned": SV_PARTITIONED}.get(mode, mode)
     s.block_qubits = int(block_qubits)
