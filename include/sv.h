@@ -63,7 +63,7 @@ enum {
     SV_ERR_INVALID_ARG = -1,   /* bad n, qubit, op, angle, schedule or pointer */
     SV_ERR_OUT_OF_MEMORY = -2, /* device or host allocation failed            */
     SV_ERR_DEVICE = -3,        /* a HIP call failed; message has the HIP error */
-    SV_ERR_UNSUPPORTED = -4,   /* valid request outside what this build does   */
+    SV_ERR_UNSUPPORTED = -4,   /* valid request the library does not support   */
     SV_ERR_BAD_HANDLE = -5     /* null or destroyed handle                     */
 };
 
