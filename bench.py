@@ -5,14 +5,16 @@ gates + 15 SWAP relabels) on a 2^32-amplitude complex64 state that is
 already resident in HBM. The JSON line reports gate-sweeps/s (gates / step
 time), effective HBM GB/s (algorithmic bytes of the passes / step time), the
 roofline of the block-pass kernel measured with HIP events on its stream, the
-plain complex128 path on the same GPU, and the FP64 oracle on the host cores.
+plain complex128 path and the other schedules on the same GPU, each with its
+error against the FP64 QPE closed form over the whole state, and the oracle
+on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+    python bench.py --cpu-full      # CPU oracle only: whole circuits, median of 3
 """
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -82,70 +84,173 @@ def time_apply(sim, gates, sched, steps, warmup, kernel_timing=False):
     return wall, dev_ms, kms, kl, st
 
 
-def qpe_check(sim, n, phi, gates, sched):
-    """Parity sample at full size: argmax and amplitudes near the peak and at
-    seeded offsets against the QPE closed form (oracle)."""
-    from oracle import qpe as cf
+class Reference:
+    """The FP64 QPE closed form (oracle), evaluated once per (n, phi) into
+    host memory when it fits, else chunk by chunk per comparison."""
 
-    sim.reset()
-    sim.apply(gates, sched)
-    t = n - 1
-    m, _, pmax = sim.qpe_readout()
-    rng = np.random.default_rng(1234)
-    starts = [max(0, min((1 << t) - 4096, cf.qpe_argmax(t, phi) - 2048))]
-    starts += [int(x) for x in rng.integers(0, (1 << t) - 4096, size=3)]
-    err = 0.0
+    def __init__(self, n, phi):
+        from oracle import timing as T
+
+        self.n, self.phi = n, phi
+        need = 16 << (n - 1)
+        self.cache = {} if T.mem_available() > 3 * need + (16 << 30) else None
+
+    def check(self, sim, gates, sched):
+        """Apply the circuit once from |0...0> and compare every amplitude."""
+        from oracle import compare as C
+        from oracle import qpe as cf
+        from paper_2605_15098_amd import sv
+
+        sim.reset()
+        sim.apply(gates, sched)
+        n, t = self.n, self.n - 1
+        m, _, pmax = sim.qpe_readout()
+        t0 = time.perf_counter()
+        ref = C.qpe_reference(n, self.phi, self.cache)
+        err = C.stream_errors(lambda o, c: sv.sv_state_range(sim.h, o, c, sim.dtype), 1 << n, ref,
+                              chunk=1 << 23)
+        out = {"argmax": int(m), "argmax_expected": cf.qpe_argmax(t, self.phi), "p_max": pmax,
+               "max_abs_err": err["max_abs"], "max_abs_err_component": err["max_abs_component"],
+               "one_minus_fidelity": err["one_minus_fidelity"], "norm_err": err["norm_err"],
+               "amplitudes_compared": 1 << n, "reference": "FP64 QPE closed form (oracle)",
+               "check_s": round(time.perf_counter() - t0, 1)}
+        return out
+
+    def drop(self):
+        self.cache = None
+
+
+def roofline(kms, kl, pass_bytes, name, workload, kernel):
+    achieved = (kl * pass_bytes) / (kms / 1000.0) / 1e9 if kl else 0.0
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(kernel, workload),
+            "algorithmic_bytes_per_launch": pass_bytes, "launches": kl,
+            "avg_launch_ms": kms / kl if kl else None}
+
+
+def hbm_reference(n, ab, block, pin, reg, reps=5):
+    """Measured ceilings on this GPU for the block pass's traffic: a plain
+    streaming copy and an in-place rewrite (sv_stream_probe) over buffers of
+    the state's size, and the block-pass kernel itself on a one-gate circuit
+    (Z on qubit 0: one pass whose only work is one phase multiply per
+    amplitude), all timed with HIP events on the current stream."""
+    import torch
     from paper_2605_15098_amd import sv
-    for s0 in starts:
-        got = sv.sv_state_range(sim.h, (1 << t) + s0, 4096, sim.dtype).astype(np.complex128)
-        want = cf.qpe_amplitudes(t, phi, np.arange(s0, s0 + 4096))
-        err = max(err, float(np.max(np.abs(got - want))))
-        zero = sv.sv_state_range(sim.h, s0, 1024, sim.dtype)
-        err = max(err, float(np.max(np.abs(zero))))
-    return {"argmax": int(m), "argmax_expected": cf.qpe_argmax(t, phi),
-            "p_max": pmax, "max_abs_err_sampled": err, "samples": 4 * 4096 + 4 * 1024}
-
-
-def cpu_baseline(n_target, phi, budget_s=20.0):
-    """The FP64 oracle on this host's cores on a bounded sample: the leading
-    gates of the same QPE circuit, on the full 2^n state when host memory
-    allows (else a smaller n, stated in `sample`)."""
-    import oracle
     from paper_2605_15098_amd import workloads as W
 
-    avail = 0
-    try:
-        with open("/proc/meminfo") as fh:
-            for line in fh:
-                if line.startswith("MemAvailable:"):
-                    avail = int(line.split()[1]) * 1024
-    except OSError:
-        pass
-    n = n_target
-    while n > 20 and (16 << n) * 1.5 > avail:
+    out = {}
+    nbytes = ab << n
+
+    def timed(fn):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            ev[1].synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        return float(np.median(ms))
+
+    half = nbytes // 2
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    a, b = buf[: half // 4], buf[half // 4:]
+    ms = timed(lambda: sv.sv_stream_probe(b, a, half, 0))
+    out["stream_copy"] = {"bytes": 2 * half, "ms": ms, "GBps": 2 * half / ms / 1e6,
+                          "what": f"copy of {half >> 30} GiB to another {half >> 30} GiB"}
+    ms = timed(lambda: sv.sv_stream_probe(buf, None, nbytes, 1))
+    out["stream_in_place"] = {"bytes": 2 * nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6,
+                              "what": f"read and rewrite of {nbytes >> 30} GiB in place"}
+    del buf, a, b
+    torch.cuda.empty_cache()
+    sim = sv.StateVector(n, "c64" if ab == 8 else "c128")
+    g = W.gates_from_tuples([("Z", 0, -1, 0.0)])
+    sched = sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg)
+    sv.sv_prepare(sim.h, g, sched, 1)
+
+    def one():
+        sim.apply(g, sched)
+    ms = timed(one)
+    st = sim.stats()
+    out["block_pass_one_gate"] = {"bytes": 2 * nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6,
+                                  "passes": st["passes"],
+                                  "what": "the block-pass kernel on a one-gate circuit (Z on qubit 0), "
+                                          "same block size, pins and register tile"}
+    sim.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(n, phi, budget_s=20.0):
+    """The oracle on this host's cores on a bounded sample of the same
+    workload: its float build (the precision of the complex64 path) applies
+    a strided sample of the 32-qubit QPE's non-SWAP gates, in circuit order,
+    to a 2^n state in one call (gate loop only; the state is allocated and
+    first-touched by the oracle's threads beforehand)."""
+    from oracle import timing as T
+    from paper_2605_15098_amd import workloads as W
+
+    while n > 20 and (8 << n) + (8 << 30) > T.mem_available():
         n -= 1
     gates = W.qpe_gates(n, phi)
-    state = oracle.zero_state(n)
-    done = 0
-    t0 = time.perf_counter()
-    for i in range(len(gates)):
-        state = oracle.apply(n, gates[i:i + 1], state)
-        if int(gates[i]["op"]) != 9:
-            done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
-    del state
-    return {"value": done / el, "unit": "gate-sweeps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {done} non-SWAP gates of the {n}-qubit QPE circuit, FP64 "
-                      f"(complex128) Algorithm 1 on the host, {el:.1f} s"}
+    body = gates[gates["op"] != 9]
+    S = T.alloc_state(n, "f32")
+    T.time_gate_loop(n, body[1:2], S, "f32")  # starts the oracle's threads
+    probe = T.time_gate_loop(n, body[1:3], S, "f32") / 2  # Hadamard-layer gates
+    k = max(1, min(len(body), int(budget_s / max(probe, 1e-6))))
+    stride = max(1, len(body) // k)
+    sample = body[::stride][:k]
+    el = T.time_gate_loop(n, sample, S, "f32")
+    del S
+    kinds = {int(o): int(np.sum(sample["op"] == o)) for o in np.unique(sample["op"])}
+    return {"value": len(sample) / el, "unit": "gate-sweeps/s", "cores": T.num_threads("f32"), "kind": "oracle",
+            "sample": f"{'every' if stride == 1 else f'every {stride}-th'} non-SWAP gate of the {n}-qubit QPE "
+                      f"circuit ({len(sample)} gates: "
+                      f"{kinds.get(7, 0)} controlled phases, {kinds.get(0, 0)} Hadamards, {kinds.get(1, 0)} X) in "
+                      f"circuit order, applied by the oracle's float build (complex64 state, the precision of "
+                      f"the GPU value) in one call on the 2^{n} state, gate loop only: {el:.1f} s",
+            "host": T.host_info()}
+
+
+def cpu_full():
+    """Whole-circuit timings of the oracle on the host: the 28-qubit QPE in
+    FP64 and in the float build, median of 3 with 2-s pauses (as the paper
+    times its runs, Section IV-B), and the 24-qubit QPE in FP64 on all threads
+    and on one thread (the scaling reference)."""
+    from oracle import timing as T
+    from paper_2605_15098_amd import workloads as W
+
+    out = {"host": T.host_info(), "runs": []}
+    for n, prec, threads in ((28, "f64", None), (28, "f32", None), (24, "f64", None), (24, "f64", 1)):
+        if (16 if prec == "f64" else 8) << n > T.mem_available() - (8 << 30):
+            out["runs"].append({"n": n, "precision": prec, "status": "not measured (host memory)"})
+            continue
+        phi = W.phi_for_seed(n)
+        gates = W.qpe_gates(n, phi)
+        G = W.qpe_gate_count(n)[0]
+        nthr = T.num_threads(prec)
+        if threads:
+            T.set_threads(threads, prec)
+        log(f"cpu-full n={n} {prec} threads={threads or nthr}")
+        med, times = T.median_of_runs(n, gates, prec)
+        if threads:
+            T.set_threads(nthr, prec)
+        rec = {"n": n, "precision": prec, "threads": threads or nthr, "gates": G, "median_s": med,
+               "times_s": times, "gate_sweeps_per_s": G / med,
+               "what": "whole QPE circuit (SWAPs included, as data moves), gate loop only, median of 3, "
+                       "2-s pauses"}
+        log(f"  {rec}")
+        out["runs"].append(rec)
+    return out
 
 
 def bench_batch(steps):
     """256 QPE instances (12..22 qubits, complex64) in one persistent launch
     under a captured graph, schedule picked by the batch autotuner."""
     import torch
+    from oracle import compare as C
     from oracle import qpe as cf
     from paper_2605_15098_amd import sv
     from paper_2605_15098_amd import workloads as W
@@ -167,27 +272,32 @@ def bench_batch(steps):
         sv.sv_apply_batch(hs, gl, best)
         dev.append(states[0].stats()["device_ms"])
     wall = (time.perf_counter() - t0) / steps
-    # correctness: every instance from |0>, argmax and sampled amplitudes
+    alg_bytes = float(sum(s.stats()["bytes"] for s in states))
+    # correctness: every instance from |0>, every amplitude against the closed form
     for s in states:
         s.reset()
     sv.sv_apply_batch(hs, gl, best)
-    worst, argmax_ok = 0.0, 0
-    rng = np.random.default_rng(99)
+    worst, worst_fid, argmax_ok = 0.0, 0.0, 0
     for s, (n, p) in zip(states, inst):
         t = n - 1
         m, _, _ = s.qpe_readout()
         argmax_ok += int(m == cf.qpe_argmax(t, p))
-        for a in (max(0, min((1 << t) - 256, cf.qpe_argmax(t, p) - 128)), int(rng.integers(0, (1 << t) - 256))):
-            got = sv.sv_state_range(s.h, (1 << t) + a, 256, "c64").astype(np.complex128)
-            worst = max(worst, float(np.max(np.abs(got - cf.qpe_amplitudes(t, p, np.arange(a, a + 256))))))
+        e = C.stream_errors(lambda o, c, s=s: sv.sv_state_range(s.h, o, c, "c64"), 1 << n,
+                            C.qpe_reference(n, p), chunk=1 << 22, threads=4)
+        worst = max(worst, e["max_abs"])
+        worst_fid = max(worst_fid, e["one_minus_fidelity"])
     for s in states:
         s.close()
     torch.cuda.empty_cache()
+    dms = float(np.median(dev))
     res = {"instances": len(inst), "qubits": [min(n for n, _ in inst), max(n for n, _ in inst)],
            "instances_per_s": len(inst) / wall, "ms_per_batch": 1000 * wall,
-           "device_ms_per_batch": float(np.median(dev)), "schedule": {"block_qubits": best.block_qubits,
-                                                                        "fuse_k": best.fuse_k},
-           "tuning_s": tune_s, "max_abs_err_sampled": worst, "argmax_exact": f"{argmax_ok}/{len(inst)}"}
+           "device_ms_per_batch": dms, "schedule": {"block_qubits": best.block_qubits, "fuse_k": best.fuse_k},
+           "algorithmic_bytes_per_batch": alg_bytes,
+           "effective_GBps_device": alg_bytes / (dms / 1000.0) / 1e9 if dms > 0 else None,
+           "hbm_frac_device": alg_bytes / (dms / 1000.0) / 1e9 / HBM_PEAK_GBPS if dms > 0 else None,
+           "tuning_s": tune_s, "max_abs_err_worst_instance": worst, "one_minus_fidelity_worst": worst_fid,
+           "argmax_exact": f"{argmax_ok}/{len(inst)}", "amplitudes_compared": "all"}
     log(f"batch: {res}")
     return res
 
@@ -204,8 +314,11 @@ def main():
     ap.add_argument("--reg", type=int, default=-1, help="register qubits per thread (default: 5 for c64)")
     ap.add_argument("--policy", default="graph", choices=("graph", "lookahead", "lru"),
                     help="gate order and block gathering (default: over the dependence graph)")
-    ap.add_argument("--quick", action="store_true", help="skip comparison runs and CPU baseline")
+    ap.add_argument("--quick", action="store_true", help="skip comparison runs, batch and CPU baseline")
+    ap.add_argument("--no-check", action="store_true", help="skip the full-state error checks")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time the CPU oracle on whole circuits (median of 3) and print that record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 4 GiB read + 4 GiB write kernel "
                          "(the reference for HBM byte counters)")
@@ -214,6 +327,9 @@ def main():
         print(f"bench.py runs on one GPU only (the build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.cpu_full:
+        print(json.dumps(cpu_full()), flush=True)
+        return
 
     import torch
     from paper_2605_15098_amd import sv
@@ -235,6 +351,7 @@ def main():
     pin = args.pin if args.pin >= 0 else (5 if c64 else 0)
     reg = args.reg if args.reg >= 0 else (5 if c64 else 0)
     sched = sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, swap_policy=args.policy)
+    ref = None if args.no_check else Reference(n, phi)
 
     log(f"workload qpe n={n} dtype={args.dtype} phi_seed={seed} gates={ngates}")
     sim = sv.StateVector(n, args.dtype)
@@ -243,11 +360,12 @@ def main():
     value = ngates / (wall / args.steps)
     eff_gbps = st["bytes"] / (wall / args.steps) / 1e9
     pass_bytes = 2.0 * ab * 2.0 ** n
-    k2_achieved = (kl[1] * pass_bytes) / (kms[1] / 1000.0) / 1e9 if kl[1] else 0.0
+    rl = roofline(kms[1], kl[1], pass_bytes, "svk2_pass_* (block-resident pass)",
+                  f"qpe{n}-{args.dtype}-{args.policy}-l{st['block_qubits']}p{pin}r{reg}", "k2")
     log(f"{ms_per_step:.2f} ms/step, {value:.1f} gate-sweeps/s, {eff_gbps:.0f} GB/s effective, "
-        f"k2 {k2_achieved:.0f} GB/s over {kl[1]} launches")
-    check = qpe_check(sim, n, phi, gates, sched)
-    log(f"parity sample: {check}")
+        f"k2 {rl['achieved']:.0f} GB/s over {kl[1]} launches")
+    check = ref.check(sim, gates, sched) if ref else None
+    log(f"parity: {check}")
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -277,21 +395,12 @@ def main():
         "effective_GBps": eff_gbps,
         "effective_hbm_frac": eff_gbps / HBM_PEAK_GBPS,
         "device_ms_per_step": dev_ms / args.steps,
-        "roofline": {
-            "kernel": "k2_kernel (block-resident pass)",
-            "bound": "hbm",
-            "achieved": k2_achieved,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": k2_achieved / HBM_PEAK_GBPS,
-            "traffic": measured_traffic("k2", f"qpe{n}-{args.dtype}-{args.policy}-l{st['block_qubits']}p{pin}r{reg}"),
-            "algorithmic_bytes_per_launch": pass_bytes,
-            "launches": kl[1],
-            "avg_launch_ms": kms[1] / kl[1] if kl[1] else None,
-        },
+        "roofline": rl,
         "parity": check,
     }
 
+    out["hbm_reference"] = hbm_reference(n, ab, block, pin, reg)
+    log(f"hbm reference: {out['hbm_reference']}")
     if args.copy_calibration:
         # one elementwise kernel that reads 4 GiB and writes 4 GiB: the
         # reference against which HBM byte counters are scaled
@@ -307,28 +416,37 @@ def main():
         for name, dt, sch, st_, wu in (
                 ("c128-plain", "c128", sv.schedule("plain"), 1, 1),
                 ("c128-partitioned", "c128", sv.schedule(), 3, 1),
+                ("c128-fused-k5", "c128", sv.schedule(fuse_k=5), 2, 1),
+                ("c64-fused-k5", "c64", sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, fuse_k=5),
+                 3, 1),
                 ("c64-partitioned-l13-pin4-reg4", "c64", sv.schedule(block_qubits=13, pin_qubits=4, reg_qubits=4),
                  4, 2),
                 ("c64-lookahead-circuit-order", "c64",
                  sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, swap_policy="lookahead"), 4, 2),
-                ("c64-fused-k5-mfma", "c64",
-                 sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, fuse_k=5), 2, 1),
                 ("c64-partitioned-outer-tier-l2-25", "c64",
                  sv.schedule(block_qubits=block, pin_qubits=pin, reg_qubits=reg, outer_qubits=25), 4, 2),
                 ("c64-plain", "c64", sv.schedule("plain"), 1, 1),
                 ("c64-paper-lru-l13", "c64", sv.paper_schedule(13), 1, 1)):
             log(f"comparison {name}")
             s2 = sv.StateVector(n, dt)
-            w2, d2, _, _, st2 = time_apply(s2, gates, sch, st_, wu)
+            w2, d2, km2, kl2, st2 = time_apply(s2, gates, sch, st_, wu, kernel_timing=(name == "c128-partitioned"))
             comps[name] = {"ms_per_step": 1000.0 * w2 / st_, "gate_sweeps_per_s": ngates / (w2 / st_),
                            "effective_GBps": st2["bytes"] / (w2 / st_) / 1e9, "passes": st2["passes"],
-                           "swaps": st2["swaps"]}
+                           "swaps": st2["swaps"], "fused_windows": st2["fused"]}
+            if name == "c128-partitioned":
+                out["roofline_c128"] = roofline(km2[1], kl2[1], 2.0 * 16 * 2.0 ** n,
+                                                "svk2_pass_* (block-resident pass, complex128)",
+                                                f"qpe{n}-c128-graph-l{st2['block_qubits']}p0r0", "k2")
+            if ref:
+                comps[name]["error"] = ref.check(s2, gates, sch)
             log(f"  {comps[name]}")
             s2.close()
             del s2
             torch.cuda.empty_cache()
         out["comparisons"] = comps
         out["speedup_vs_c128_plain"] = value / comps["c128-plain"]["gate_sweeps_per_s"]
+    if ref:
+        ref.drop()
     if not args.quick:
         out["batch_qpe256"] = bench_batch(args.steps)
     if not args.quick and not args.no_cpu:

@@ -44,6 +44,8 @@
  *                       in two halves for blocks above 64 KiB; 2: in halves
  *                       whenever possible (tests)
  *   SV_TRACE_HOST       print host-side upload and launch timings to stderr
+ *   SV_K2_MAX_GRID      at most this many work-groups per block-pass launch
+ *                       (each walks more blocks; same bits; tests)
  */
 #ifndef SVMI_SV_H_INCLUDED
 #define SVMI_SV_H_INCLUDED
@@ -367,6 +369,13 @@ sv_status sv_set_kernel_timing(sv_handle h, int on);
 
 /* Permutation of the current layout: l2p[q] = physical bit of qubit q. */
 sv_status sv_layout(sv_handle h, int *l2p);
+
+/* Bandwidth reference for the block passes (not part of the simulation): a
+ * plain streaming kernel over DEVICE buffers of `bytes` (a multiple of 16,
+ * 16-byte aligned). mode 0 copies src to dst (bytes read + bytes written);
+ * mode 1 rewrites dst in place (src unused), the access pattern of a block
+ * pass. Stream-ordered on `stream` (NULL = null stream). */
+sv_status sv_stream_probe(void *dst, const void *src, size_t bytes, int mode, void *stream);
 
 /* Testing hook: make the next device allocation (kind 1) or kernel launch
  * (kind 2) of this process fail; 0 clears. */

@@ -24,6 +24,11 @@
  * -ffp-contract=off).
  *
  * State arrays are 2^n interleaved (re, im) doubles in logical order.
+ *
+ * Built with -DOR_FLOAT the same source keeps the state in binary32 (gate
+ * matrices still formed in binary64, rounded once): that build exists only to
+ * time the method at the precision of the complex64 GPU path (the paper ran
+ * single precision throughout); it is never used as a reference.
  */
 #include <math.h>
 #include <stdint.h>
@@ -32,6 +37,12 @@
 
 #ifdef _OPENMP
 #include <omp.h>
+#endif
+
+#ifdef OR_FLOAT
+typedef float or_real;
+#else
+typedef double or_real;
 #endif
 
 /* Gate kinds, numbered as in the gate records the workload generator writes. */
@@ -75,19 +86,19 @@ int or_gate_matrix(int op, double theta, const double *u_in, double *u)
 }
 
 /* One Algorithm-1 iteration body on the pair (j, j + 2^t). */
-static inline void pair_update(double *S, uint64_t j, uint64_t h, const double *u)
+static inline void pair_update(or_real *S, uint64_t j, uint64_t h, const or_real *u)
 {
-    const double ar = S[2 * j], ai = S[2 * j + 1];
-    const double br = S[2 * (j + h)], bi = S[2 * (j + h) + 1];
+    const or_real ar = S[2 * j], ai = S[2 * j + 1];
+    const or_real br = S[2 * (j + h)], bi = S[2 * (j + h) + 1];
     /* S[j] = U11 a + U12 b ; S[j+h] = U21 a + U22 b */
-    const double r0 = (u[0] * ar - u[1] * ai) + (u[2] * br - u[3] * bi);
-    const double i0 = (u[0] * ai + u[1] * ar) + (u[2] * bi + u[3] * br);
+    const or_real r0 = (u[0] * ar - u[1] * ai) + (u[2] * br - u[3] * bi);
+    const or_real i0 = (u[0] * ai + u[1] * ar) + (u[2] * bi + u[3] * br);
 #if OR_MUTANT == 4
-    const double r1 = (u[4] * ar - u[5] * ai) + (u[6] * br + u[7] * bi); /* dropped conj sign */
+    const or_real r1 = (u[4] * ar - u[5] * ai) + (u[6] * br + u[7] * bi); /* dropped conj sign */
 #else
-    const double r1 = (u[4] * ar - u[5] * ai) + (u[6] * br - u[7] * bi);
+    const or_real r1 = (u[4] * ar - u[5] * ai) + (u[6] * br - u[7] * bi);
 #endif
-    const double i1 = (u[4] * ai + u[5] * ar) + (u[6] * bi + u[7] * br);
+    const or_real i1 = (u[4] * ai + u[5] * ar) + (u[6] * bi + u[7] * br);
     S[2 * j] = r0; S[2 * j + 1] = i0;
     S[2 * (j + h)] = r1; S[2 * (j + h) + 1] = i1;
 }
@@ -96,7 +107,7 @@ static inline void pair_update(double *S, uint64_t j, uint64_t h, const double *
  * amplitudes. The pair index p enumerates exactly the (i, j) iterations of
  * the two loops (j = i + low part, i = high part shifted past bit t); the
  * iterations are independent, so they are distributed over threads. */
-static void apply_alg1(double *S, int n, int t, int c, const double *u)
+static void apply_alg1(or_real *S, int n, int t, int c, const or_real *u)
 {
     const uint64_t h = 1ull << t;
     const int64_t npairs = (int64_t)(1ull << (n - 1));
@@ -115,7 +126,7 @@ static void apply_alg1(double *S, int n, int t, int c, const double *u)
 }
 
 /* SWAP of qubits a and b: exchange the amplitudes whose bits a and b differ. */
-static void apply_swap(double *S, int n, int a, int b)
+static void apply_swap(or_real *S, int n, int a, int b)
 {
     const uint64_t N = 1ull << n;
 #pragma omp parallel for schedule(static) if (n >= 14)
@@ -124,7 +135,7 @@ static void apply_swap(double *S, int n, int a, int b)
         const uint64_t ba = (i >> a) & 1ull, bb = (i >> b) & 1ull;
         if (ba == 1 && bb == 0) {
             const uint64_t k = i ^ (1ull << a) ^ (1ull << b);
-            double tr = S[2 * i], ti = S[2 * i + 1];
+            or_real tr = S[2 * i], ti = S[2 * i + 1];
             S[2 * i] = S[2 * k]; S[2 * i + 1] = S[2 * k + 1];
             S[2 * k] = tr; S[2 * k + 1] = ti;
         }
@@ -144,20 +155,34 @@ static int check_gate(int n, int op, int t, int c, int t2)
  * Gate g is (op[g], tgt[g], ctl[g] (-1 none), tgt2[g] (SWAP), theta[g],
  * u[8g..8g+7] for OR_U2). Returns 0, or -1 on a malformed gate (nothing
  * after it is applied). */
-int or_apply(int n, double *S, int m, const int *op, const int *tgt, const int *ctl,
+int or_apply(int n, or_real *S, int m, const int *op, const int *tgt, const int *ctl,
              const int *tgt2, const double *theta, const double *u)
 {
     double U[8];
+    or_real Ur[8];
     if (n < 1 || n > 40) return -1;
     for (int g = 0; g < m; ++g) {
         if (check_gate(n, op[g], tgt[g], ctl[g], tgt2[g])) return -1;
         if (op[g] == OR_SWAP) { apply_swap(S, n, tgt[g], tgt2[g]); continue; }
         if (or_gate_matrix(op[g], theta[g], u + 8 * g, U)) return -1;
-        apply_alg1(S, n, tgt[g], ctl[g], U);
+        for (int k = 0; k < 8; ++k) Ur[k] = (or_real)U[k];
+        apply_alg1(S, n, tgt[g], ctl[g], Ur);
     }
     return 0;
 }
 
+/* |0...0> in S, written by the same static thread partition that the gate
+ * loops use, so each page is first touched by the thread (and NUMA node)
+ * that later sweeps it. */
+void or_zero_state(int n, or_real *S)
+{
+    const int64_t N = (int64_t)(1ull << n);
+#pragma omp parallel for schedule(static) if (n >= 14)
+    for (int64_t i = 0; i < N; ++i) { S[2 * i] = 0; S[2 * i + 1] = 0; }
+    S[0] = 1;
+}
+
+#ifndef OR_FLOAT
 /* |S_i|^2 in binary64. */
 void or_probabilities(int n, const double *S, double *P)
 {
@@ -289,11 +314,23 @@ int or_apply_partitioned(int n, int l, double *S, int m, const int *op, const in
     return 0;
 }
 
+#endif /* !OR_FLOAT: readouts and the partitioned method are binary64 only */
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the later parallel loops (timing a one-thread reference). */
+void or_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
 #endif
 }

@@ -445,6 +445,16 @@ const char *sv_version(void) { return "svmi 0.1 (gfx950)"; }
 
 const char *sv_last_error(void) { return g_err.c_str(); }
 
+sv_status sv_stream_probe(void *dst, const void *src, size_t bytes, int mode, void *stream)
+{
+    if (!dst || (mode == 0 && !src)) return fail(SV_ERR_INVALID_ARG, "null buffer");
+    if (mode != 0 && mode != 1) return fail(SV_ERR_INVALID_ARG, "mode must be 0 (copy) or 1 (in place)");
+    if (bytes % 16 != 0 || ((uintptr_t)dst % 16) != 0 || (mode == 0 && ((uintptr_t)src % 16) != 0))
+        return fail(SV_ERR_INVALID_ARG, "buffers and size must be 16-byte aligned");
+    SV_HIP(svk::stream_probe(dst, src, bytes, mode, (hipStream_t)stream), "stream probe");
+    return SV_OK;
+}
+
 sv_status sv_debug_inject_fault(int kind)
 {
     if (kind < 0 || kind > 2) return fail(SV_ERR_INVALID_ARG, "unknown fault kind");

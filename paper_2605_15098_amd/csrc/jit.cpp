@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <unistd.h>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <sstream>
 #include <string>
@@ -53,6 +54,11 @@ std::string hexd(double x)
 
 std::string u64s(uint64_t x) { return std::to_string(x) + "ull"; }
 
+// The compile options of every pass module.
+const char *const kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                                "-target-feature", "-Xclang", "-packed-fp32-ops"};
+constexpr int kRtcNopts = (int)(sizeof kRtcOpts / sizeof kRtcOpts[0]);
+
 }  // namespace
 
 namespace svj {
@@ -60,7 +66,6 @@ namespace svj {
 static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int dtype, int idx)
 {
     const int r = s.logr, l = s.l;
-    const int R = 1 << r;
     std::ostringstream o;
     o << "struct Prog" << idx << " {\n  template <typename T, int LOGR>\n"
          "  __device__ __forceinline__ void run(typename CT<T>::type *a, K2Ctx &cx) const {\n"
@@ -86,23 +91,48 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
             break;
         }
         case svp::K2_DIAGRUN: {
-            const svp::DiagRec *rec = reinterpret_cast<const svp::DiagRec *>(plan.table.data() + op.a);
-            const double *qt = reinterpret_cast<const double *>(rec + 1);
+            // Thread factors shared along a depth-first walk of the subsets
+            // of the register bits: slot k's product extends its parent's
+            // (k without its highest bit) by the groups whose highest bit is
+            // that bit, which is the fold order DiagRun defines, so the
+            // interpreter's slot-by-slot products have the same bits.
+            const svp::DiagRun *rec = reinterpret_cast<const svp::DiagRun *>(plan.table.data() + op.a);
+            const svp::DiagGroup *gs = reinterpret_cast<const svp::DiagGroup *>(rec + 1);
+            const double *qt = reinterpret_cast<const double *>(gs + rec->ngroups);
+            auto top_bit = [](int m) { return m ? 31 - __builtin_clz((uint32_t)m) : -1; };
             o << "    {\n";
-            if (rec->has_group) {
-                const svp::DiagGroup &G = rec->g;
-                o << "      const svp::DiagGroup G{" << G.rmask << ", " << G.cond_kind << ", " << G.cond_bit << ", "
-                  << G.uidx << ", " << G.lane_off << ", " << G.wave_off << ", 0, 0};\n"
-                  << "      const C fc = k2_group_factor<C>(G, cx);\n";
-            } else {
-                o << "      const C fc = mk<C>(1.0, 0.0);\n";
+            for (int i = 0; i < rec->ngroups; ++i) {
+                const svp::DiagGroup &G = gs[i];
+                o << "      const svp::DiagGroup G" << i << "{" << G.rmask << ", " << G.cond_kind << ", " << G.cond_bit
+                  << ", " << G.uidx << ", " << G.lane_off << ", " << G.wave_off << ", 0, 0};\n"
+                  << "      const C g" << i << " = k2_group_factor<C>(G" << i << ", cx);\n";
             }
-            for (int k = 0; k < R; ++k) {
-                if (!((rec->kmask >> k) & 1u)) continue;
-                const bool q = (rec->qmask >> k) & 1u;
-                o << "      k2_diag_amp(a[" << k << "], " << (q ? "true" : "false") << ", make_double2("
-                  << hexd(qt[2 * k]) << ", " << hexd(qt[2 * k + 1]) << "), fc);\n";
-            }
+            int tmp = 0;
+            auto fold = [&](std::string t, int i) -> std::string {
+                if (t.empty()) return "g" + std::to_string(i);
+                const std::string name = "t" + std::to_string(tmp++);
+                o << "      const C " << name << " = cmul(" << t << ", g" << i << ");\n";
+                return name;
+            };
+            std::string troot;
+            for (int i = 0; i < rec->ngroups; ++i)
+                if (gs[i].rmask == 0) troot = fold(troot, i);
+            std::function<void(int, const std::string &)> visit = [&](int k, const std::string &tk) {
+                if ((rec->kmask >> k) & 1u) {
+                    const bool q = (rec->qmask >> k) & 1u;
+                    o << "      k2_diag_apply(a[" << k << "], " << (q ? "true" : "false") << ", make_double2("
+                      << hexd(qt[2 * k]) << ", " << hexd(qt[2 * k + 1]) << "), " << (tk.empty() ? "false" : "true")
+                      << ", " << (tk.empty() ? std::string("mk<C>(1.0, 0.0)") : tk) << ");\n";
+                }
+                for (int j = top_bit(k) + 1; j < r; ++j) {
+                    const int c = k | (1 << j);
+                    std::string tc = tk;
+                    for (int i = 0; i < rec->ngroups; ++i)
+                        if (top_bit(gs[i].rmask) == j && (gs[i].rmask & ~c) == 0) tc = fold(tc, i);
+                    visit(c, tc);
+                }
+            };
+            visit(0, troot);
             o << "    }\n";
             break;
         }
@@ -183,9 +213,7 @@ static hipError_t compile_rtc(const std::string &src, std::vector<char> &code, s
         if (err) *err = "hiprtcCreateProgram failed";
         return hipErrorInvalidValue;
     }
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
-                          "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    const hiprtcResult rc = hiprtcCompileProgram(prog, 8, opts);
+    const hiprtcResult rc = hiprtcCompileProgram(prog, kRtcNopts, kRtcOpts);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
@@ -217,6 +245,22 @@ static uint64_t fnv1a(const std::string &s, uint64_t h)
     return h;
 }
 
+// Hash of everything a module depends on besides its generated source: the
+// embedded header texts (handlers, skeleton, K2Args layout) and the options.
+static uint64_t toolchain_hash()
+{
+    std::string t = kJitAbiH;
+    t += '\0';
+    t += kJitDeviceH;
+    for (int i = 0; i < kRtcNopts; ++i) {
+        t += '\0';
+        t += kRtcOpts[i];
+    }
+    return fnv1a(t, 0xcbf29ce484222325ull);
+}
+
+// <dir>/svk2-<source hash x2>-<toolchain hash>.co; the source hashes also
+// cover the hipRTC version.
 static std::string cache_path(const std::string &src)
 {
     const char *dir = std::getenv("SV_JIT_CACHE_DIR");
@@ -224,9 +268,10 @@ static std::string cache_path(const std::string &src)
     int major = 0, minor = 0;
     hiprtcVersion(&major, &minor);
     const std::string tag = src + "|hiprtc " + std::to_string(major) + "." + std::to_string(minor);
-    char name[64];
-    std::snprintf(name, sizeof name, "/svk2-%016llx%016llx.co", (unsigned long long)fnv1a(tag, 0xcbf29ce484222325ull),
-                  (unsigned long long)fnv1a(tag, 0x84222325cbf29ce4ull));
+    char name[96];
+    std::snprintf(name, sizeof name, "/svk2-%016llx%016llx-%016llx.co",
+                  (unsigned long long)fnv1a(tag, 0xcbf29ce484222325ull),
+                  (unsigned long long)fnv1a(tag, 0x84222325cbf29ce4ull), (unsigned long long)toolchain_hash());
     return std::string(dir) + name;
 }
 
@@ -263,10 +308,8 @@ std::string compile_check(const std::string &src)
     const char *names[] = {"k2_abi.h", "k2_device.h"};
     if (hiprtcCreateProgram(&prog, src.c_str(), "svk2_pass.hip", 2, headers, names) != HIPRTC_SUCCESS)
         return "hiprtcCreateProgram failed";
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
-                          "-target-feature", "-Xclang", "-packed-fp32-ops"};
     std::string out;
-    if (hiprtcCompileProgram(prog, 8, opts) != HIPRTC_SUCCESS) {
+    if (hiprtcCompileProgram(prog, kRtcNopts, kRtcOpts) != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
         out.assign(ls, '\0');
@@ -330,8 +373,7 @@ hipError_t launch(const void *handle, void *S, const svp::K2Args &a, hipStream_t
 {
     const Kernel &e = *static_cast<const Kernel *>(handle);
     const uint64_t blocks = 1ull << a.nblk_bits;
-    uint64_t grid = (uint64_t)e.per_cu * (uint64_t)g_cus;
-    if (grid > blocks) grid = blocks;
+    const uint64_t grid = svp::k2_grid((uint64_t)e.per_cu * (uint64_t)g_cus, blocks);
     svp::K2Args args = a;
     void *params[] = {&S, &args};
     return hipModuleLaunchKernel(e.fn, (unsigned)grid, 1, 1, e.threads, 1, 1, 0, st, params, nullptr);

@@ -32,7 +32,7 @@ enum K2Kind {
                      // v[0..1]: factor
     K2_DIAG = 5,     // a: target slot or -1; b: target bit code when a < 0;
                      // c: slot mask; m0/m1 as K2_PHASE; v[0..1] d0, v[2..3] d1
-    K2_DIAGRUN = 6,  // a: byte offset of a DiagRec in the table buffer
+    K2_DIAGRUN = 6,  // a: byte offset of a DiagRun in the table buffer
     K2_HU = 7,       // unnormalized Hadamard (a+b, a-b) on slot a, no control
     K2_SCALE = 8,    // every amplitude times v[0]
     K2_MFMA = 9,     // dense window unitary through the matrix cores: a: byte
@@ -64,16 +64,22 @@ struct DiagGroup {
     int32_t pad0, pad1;
 };
 
-// One op of a diagonal run; followed in the table by 2^r complex doubles Q[k]:
-// the constant factor of register pattern k. Amplitude slot k in kmask is
-// multiplied by (k in qmask ? Q[k] : 1) * (has_group ? group factor : 1).
-// The planner guarantees that a group covers every slot in kmask.
-struct DiagRec {
+// A run of diagonal gates as one multiply per register slot. Followed in the
+// table by ngroups DiagGroup records (sorted by the highest bit of rmask,
+// groups with rmask = 0 first) and then 2^r complex doubles Q[k], the
+// constant factor of register pattern k. Register slot k is multiplied (when
+// k is in kmask) by F(k) = Q[k] * T(k) if k is in qmask, else T(k), where the
+// thread factor T(k) folds, in this order, the groups with rmask = 0 and then,
+// for each set bit b of k ascending, the groups whose highest rmask bit is b
+// and whose rmask lies within k (each in record order; T = g for the first
+// factor, T = T * g after). Folding in this fixed order lets a compiled pass
+// share T between slots along a walk of the subsets of the register bits and
+// still give the same bits as a slot-by-slot evaluation.
+struct DiagRun {
     uint32_t kmask;
     uint32_t qmask;
-    int32_t has_group;
+    int32_t ngroups;
     int32_t pad;
-    DiagGroup g;
 };
 
 // Block-uniform factor: e^{2 pi i sum angle_j [base covers tmask_j]} with

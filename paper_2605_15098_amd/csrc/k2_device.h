@@ -449,25 +449,48 @@ __device__ __forceinline__ C k2_group_factor(const svp::DiagGroup &G, const K2Ct
     return f;
 }
 
-// One amplitude of a diagonal run: times the group factor fc, or times
-// Q[k] * fc when the slot has a constant factor.
-template <typename C>
-__device__ __forceinline__ void k2_diag_amp(C &ak, bool with_q, double2 q, C fc)
+// One factor of a run's fold (DiagRun): T = g for the first, T = T * g after.
+template <typename C> __device__ __forceinline__ C k2_fold(bool first, C T, C g)
 {
-    const C Fk = with_q ? cmul(mk<C>(q.x, q.y), fc) : fc;
-    ak = cmul(Fk, ak);
+    return first ? g : cmul(T, g);
 }
 
-template <int R, typename C>
-__device__ __forceinline__ void k2_diagrun(C *a, const K2Ctx &cx, const svp::DiagRec *rec)
+// Slot k's multiply of a diagonal run: F = Q[k] * T (or Q[k] when no group
+// covers k, or T without a constant), a[k] = F * a[k].
+template <typename C> __device__ __forceinline__ void k2_diag_apply(C &ak, bool with_q, double2 q, bool have_t, C T)
 {
-    const double2 *qt = reinterpret_cast<const double2 *>(rec + 1);
+    const C qc = mk<C>(q.x, q.y);
+    const C F = with_q ? (have_t ? cmul(qc, T) : qc) : T;
+    ak = cmul(F, ak);
+}
+
+// A diagonal run evaluated slot by slot (the interpreter): each slot folds
+// its groups in the record's canonical order (see DiagRun), recomputing the
+// group factors it needs.
+template <int LOGR, typename C>
+__device__ __forceinline__ void k2_diagrun(C *a, const K2Ctx &cx, const svp::DiagRun *rec)
+{
+    constexpr int R = 1 << LOGR;
+    const svp::DiagGroup *gs = reinterpret_cast<const svp::DiagGroup *>(rec + 1);
+    const int ng = rec->ngroups;
+    const double2 *qt = reinterpret_cast<const double2 *>(gs + ng);
     const uint32_t kmask = rec->kmask, qmask = rec->qmask;
-    const C fc = rec->has_group ? k2_group_factor<C>(rec->g, cx) : mk<C>(1.0, 0.0);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         if (!((kmask >> k) & 1u)) continue;
-        k2_diag_amp(a[k], ((qmask >> k) & 1u) != 0, qt[k], fc);
+        C T = mk<C>(1.0, 0.0);
+        bool have = false;
+        for (int b = -1; b < LOGR; ++b) {
+            if (b >= 0 && !((k >> b) & 1)) continue;
+            for (int i = 0; i < ng; ++i) {
+                const int rm = gs[i].rmask;
+                const int top = rm ? 31 - __builtin_clz((uint32_t)rm) : -1;
+                if (top != b || (rm & ~k)) continue;
+                T = k2_fold(!have, T, k2_group_factor<C>(gs[i], cx));
+                have = true;
+            }
+        }
+        k2_diag_apply(a[k], ((qmask >> k) & 1u) != 0, qt[k], have, T);
     }
 }
 
@@ -696,9 +719,17 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
                 uint64_t acc = 0;
                 for (int j = 0; j < ugrp[g].nterms; ++j)
                     if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
-                double sn, cs;
-                sincospi(ldexp((double)(int64_t)acc, -63), &sn, &cs);
-                ufac[g] = make_double2(cs, sn);
+                if constexpr (sizeof(T) == 4) {
+                    // complex64: the factor is rounded to FP32 anyway; the
+                    // top 32 bits of the turn count give it to 2^-31 half-turns
+                    float sn, cs;
+                    sincospif(ldexpf((float)(int32_t)(acc >> 32), -31), &sn, &cs);
+                    ufac[g] = make_double2(cs, sn);
+                } else {
+                    double sn, cs;
+                    sincospi(ldexp((double)(int64_t)acc, -63), &sn, &cs);
+                    ufac[g] = make_double2(cs, sn);
+                }
             }
             lds_barrier();
         }
@@ -780,7 +811,7 @@ struct K2Interp {
                 default: break;
                 }
             } else if (kind == svp::K2_DIAGRUN) {
-                k2_diagrun<R>(a, cx, reinterpret_cast<const svp::DiagRec *>(cx.table + op.a));
+                k2_diagrun<LOGR>(a, cx, reinterpret_cast<const svp::DiagRun *>(cx.table + op.a));
             } else if (kind == svp::K2_LAYOUT) {
                 int nrb[LOGR];
 #pragma unroll

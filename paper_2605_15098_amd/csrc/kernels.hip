@@ -322,8 +322,7 @@ static hipError_t k2_launch_t(void *S, const K2Args &a, const svp::K2Op *ops, hi
                                                                 (int)threads, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    uint64_t grid = (uint64_t)per_cu * (uint64_t)cus;
-    if (grid > blocks) grid = blocks;
+    const uint64_t grid = svp::k2_grid((uint64_t)per_cu * (uint64_t)cus, blocks);
     k2_kernel<T, LOGR, MFMA><<<(unsigned)grid, threads, lds, st>>>((C *)S, ops, a);
     return hipGetLastError();
 }
@@ -350,6 +349,52 @@ hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const s
                           : k2_dispatch<double, true>(S, logr, a, ops, st);
     return dtype == 0 ? k2_dispatch<float, false>(S, logr, a, ops, st)
                       : k2_dispatch<double, false>(S, logr, a, ops, st);
+}
+
+// ---------------------------------------------------------------- bandwidth probe
+
+// Plain HBM streams, the reference for the block passes' bandwidth: mode 0
+// copies src to dst, mode 1 rewrites dst in place (read and write of the
+// same addresses, as a block pass does). 16-byte accesses, four in flight
+// per thread, grid-stride over whole-device work-groups.
+__global__ void __launch_bounds__(256) stream_probe_kernel(float4 *__restrict__ dst, const float4 *__restrict__ src,
+                                                            uint64_t n16, float scale)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        float4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = src[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k].x *= scale;
+            v[k].y *= scale;
+            v[k].z *= scale;
+            v[k].w *= scale;
+            dst[i + k * stride] = v[k];
+        }
+    }
+    for (; i < n16; i += stride) {
+        float4 v = src[i];
+        v.x *= scale;
+        v.y *= scale;
+        v.z *= scale;
+        v.w *= scale;
+        dst[i] = v;
+    }
+}
+
+hipError_t stream_probe(void *dst, const void *src, uint64_t bytes, int mode, hipStream_t st)
+{
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const uint64_t n16 = bytes / 16;
+    const unsigned grid = grid_for(n16, 256, (unsigned)cus * 8u);
+    stream_probe_kernel<<<grid, 256, 0, st>>>((float4 *)dst, (const float4 *)(mode == 1 ? dst : src), n16, 1.0f);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- k5 readouts

@@ -30,6 +30,9 @@ hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st);
 hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *dev_ops, bool mfma,
                    hipStream_t st);
 
+// Plain HBM stream (bandwidth reference): mode 0 copy, 1 in place.
+hipError_t stream_probe(void *dst, const void *src, uint64_t bytes, int mode, hipStream_t st);
+
 // Readouts (FP64). perm: HOST array of n ints, perm[q] = physical bit of
 // logical bit q, or nullptr for the identity (passed to the kernel by value).
 hipError_t probabilities(const void *S, int n, int dtype, const int *perm, double *out,

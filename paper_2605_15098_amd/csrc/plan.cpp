@@ -166,8 +166,8 @@ struct Builder {
         uint64_t angle;
     };
 
-    // Emit a run of diagonal gates as K2_DIAGRUN ops for the current layout.
-    // Returns false when a gate has non-unit entries (caller emits K2_DIAG).
+    // Emit a run of unit-modulus diagonal gates as one K2_DIAGRUN op for the
+    // current layout.
     void emit_diag_run(const std::vector<MGate> &run, const std::vector<int> &rank,
                        const std::vector<int> &rb, std::vector<UGroup> &ugroups,
                        std::vector<UTerm> &uterms)
@@ -281,8 +281,9 @@ struct Builder {
             ptab.insert(ptab.end(), tab.begin(), tab.end());
             return idx;
         };
-        // One op per factor group; constant factors ride with the first op
-        // whose group covers their slots, the rest get an op of their own.
+        // One op for the whole run (DiagRun): its groups sorted by the
+        // highest register bit they need (groups without one first), the
+        // slots any group or constant touches, and the constants.
         const uint32_t all = (uint32_t)((1ull << qang.size()) - 1ull);
         auto cover = [&](int rmask) {
             uint32_t m = 0;
@@ -290,28 +291,13 @@ struct Builder {
                 if ((int(k) & rmask) == rmask) m |= 1u << k;
             return m;
         };
-        uint32_t qpend = 0;
-        for (size_t k = 0; k < qang.size(); ++k)
-            if (qang[k] != 0) qpend |= 1u << k;
-        std::vector<double> q(2 * qang.size());
-        for (size_t k = 0; k < qang.size(); ++k) cexp(qang[k], &q[2 * k]);
-        auto put = [&](const DiagRec &rec) {
-            std::vector<uint8_t> blob(sizeof(DiagRec) + q.size() * sizeof(double));
-            std::memcpy(blob.data(), &rec, sizeof(DiagRec));
-            std::memcpy(blob.data() + sizeof(DiagRec), q.data(), q.size() * sizeof(double));
-            K2Op op{};
-            op.kind = K2_DIAGRUN;
-            op.a = table_put(blob.data(), blob.size());
-            plan.ops.push_back(op);
-        };
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-            GroupAcc &G = groups[gi];
-            DiagRec rec{};
-            rec.has_group = 1;
-            rec.kmask = cover(G.rmask) & all;
-            rec.qmask = rec.kmask & qpend;
-            qpend &= ~rec.qmask;
-            DiagGroup &d = rec.g;
+        auto top_bit = [](int rmask) { return rmask ? 31 - __builtin_clz((uint32_t)rmask) : -1; };
+        std::stable_sort(groups.begin(), groups.end(),
+                         [&](const GroupAcc &x, const GroupAcc &y) { return top_bit(x.rmask) < top_bit(y.rmask); });
+        DiagRun head{};
+        std::vector<DiagGroup> recs;
+        for (GroupAcc &G : groups) {
+            DiagGroup d{};
             d.rmask = G.rmask;
             d.cond_kind = G.cond_kind;
             d.cond_bit = G.cond_bit;
@@ -326,15 +312,27 @@ struct Builder {
                 d.uidx = (int)ugroups.size();
                 ugroups.push_back(ug);
             }
-            put(rec);
+            head.kmask |= cover(G.rmask) & all;
+            recs.push_back(d);
         }
-        if (qpend != 0) {
-            DiagRec rec{};
-            rec.has_group = 0;
-            rec.kmask = qpend;
-            rec.qmask = qpend;
-            put(rec);
-        }
+        for (size_t k = 0; k < qang.size(); ++k)
+            if (qang[k] != 0) head.qmask |= 1u << k;
+        head.kmask |= head.qmask;
+        head.ngroups = (int)recs.size();
+        if (head.kmask == 0) return;
+        std::vector<double> q(2 * qang.size());
+        for (size_t k = 0; k < qang.size(); ++k) cexp(qang[k], &q[2 * k]);
+        std::vector<uint8_t> blob(sizeof(DiagRun) + recs.size() * sizeof(DiagGroup) + q.size() * sizeof(double));
+        uint8_t *w = blob.data();
+        std::memcpy(w, &head, sizeof(DiagRun));
+        w += sizeof(DiagRun);
+        if (!recs.empty()) std::memcpy(w, recs.data(), recs.size() * sizeof(DiagGroup));
+        w += recs.size() * sizeof(DiagGroup);
+        std::memcpy(w, q.data(), q.size() * sizeof(double));
+        K2Op op{};
+        op.kind = K2_DIAGRUN;
+        op.a = table_put(blob.data(), blob.size());
+        plan.ops.push_back(op);
     }
 
     // LDS of one work-group on gfx950.

@@ -22,6 +22,7 @@
 #pragma once
 
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -47,7 +48,7 @@ struct MGate {
 
 static_assert(sizeof(K2Op) == 96, "K2Op layout");
 static_assert(sizeof(DiagGroup) == 32, "DiagGroup layout");
-static_assert(sizeof(DiagRec) == 48, "DiagRec layout");
+static_assert(sizeof(DiagRun) == 16, "DiagRun layout");
 
 enum StepKind {
     ST_K1 = 0,  // one plain sweep for one gate
@@ -94,7 +95,7 @@ struct PlanStats {
 struct Plan {
     std::vector<Step> steps;
     std::vector<K2Op> ops;
-    std::vector<uint8_t> table;      // DiagRec, lane/wave tables, UGroup, UTerm
+    std::vector<uint8_t> table;      // DiagRun, lane/wave tables, UGroup, UTerm
     PlanStats stats;
     std::vector<int> l2p_after;      // layout after the plan
     int l = 0;
@@ -126,5 +127,19 @@ std::string make_plan(const PlanConfig &cfg, const RawGate *gates, size_t m,
 
 // Angle in turns -> 64-bit fixed point (mod one turn).
 uint64_t turns_fixed(double turns);
+
+// Work-groups of one block-pass launch: the resident work-groups (the
+// persistent grid), at most one per block, and at most SV_K2_MAX_GRID when
+// that is set to a positive number, so that each work-group walks many
+// blocks even on a small state (tests of the block loop's reload paths).
+inline uint64_t k2_grid(uint64_t resident, uint64_t blocks)
+{
+    uint64_t g = resident < blocks ? resident : blocks;
+    if (const char *e = std::getenv("SV_K2_MAX_GRID")) {
+        const long long cap = std::atoll(e);
+        if (cap > 0 && (uint64_t)cap < g) g = (uint64_t)cap;
+    }
+    return g < 1 ? 1 : g;
+}
 
 }  // namespace svp

@@ -144,6 +144,7 @@ _SIGS = {
     "sv_layout": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int32),
     "sv_set_kernel_timing": ([_VP, ctypes.c_int], ctypes.c_int32),
     "sv_debug_inject_fault": ([ctypes.c_int], ctypes.c_int32),
+    "sv_stream_probe": ([_VP, _VP, ctypes.c_size_t, ctypes.c_int, _VP], ctypes.c_int32),
 }
 
 
@@ -449,6 +450,12 @@ def sv_layout(h, n: int):
     a = (ctypes.c_int * n)()
     _check(load().sv_layout(_VP(h), a))
     return list(a)
+
+
+def sv_stream_probe(dst, src, nbytes: int, mode: int = 0, stream=None) -> None:
+    """Plain HBM stream over device tensors (mode 0 copy, 1 in place)."""
+    _check(load().sv_stream_probe(_VP(_dptr(dst)), _VP(_dptr(src)) if src is not None else None, int(nbytes),
+                                  int(mode), _VP(_stream(stream))))
 
 
 def sv_debug_inject_fault(kind: int) -> None:

@@ -232,34 +232,44 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
                     }
                 }
             } else if (op.kind == K2_DIAGRUN) {
-                const DiagRec *rec = reinterpret_cast<const DiagRec *>(table + op.a);
-                const double *qt = reinterpret_cast<const double *>(rec + 1);
+                const DiagRun *rec = reinterpret_cast<const DiagRun *>(table + op.a);
+                const DiagGroup *gs = reinterpret_cast<const DiagGroup *>(rec + 1);
+                const double *qt = reinterpret_cast<const double *>(gs + rec->ngroups);
+                // record invariants: groups sorted by their highest register
+                // bit, every slot a group or a constant touches is multiplied
+                auto top = [](int m) { return m ? 31 - __builtin_clz((uint32_t)m) : -1; };
+                for (int i = 1; i < rec->ngroups; ++i)
+                    if (top(gs[i - 1].rmask) > top(gs[i].rmask)) return_error = true;
+                if ((rec->qmask & ~rec->kmask) != 0) return_error = true;
+                for (int i = 0; i < rec->ngroups; ++i)
+                    for (int k = 0; k < R; ++k)
+                        if ((k & gs[i].rmask) == gs[i].rmask && !((rec->kmask >> k) & 1u)) return_error = true;
+                const double *ptab = reinterpret_cast<const double *>(table + st.tab_off);
                 for (int tid = 0; tid < NT; ++tid) {
-                    cd f(1, 0);
-                    if (rec->has_group) {
-                        const DiagGroup &G = rec->g;
+                    std::vector<cd> gf(rec->ngroups, cd(1, 0));
+                    for (int i = 0; i < rec->ngroups; ++i) {
+                        const DiagGroup &G = gs[i];
                         bool on = true;
                         if (G.cond_kind == 1) on = (base >> G.cond_bit) & 1ull;
                         else if (G.cond_kind == 2) on = (tid >> G.cond_bit) & 1;
-                        if (on) {
-                            if (G.uidx >= 0) f = ufac[G.uidx];
-                            const double *ptab = reinterpret_cast<const double *>(table + st.tab_off);
-                            if (G.wave_off >= 0) {
-                                const double *w = ptab + 2 * G.wave_off;
-                                f *= cd(w[2 * (tid >> 6)], w[2 * (tid >> 6) + 1]);
-                            }
-                            if (G.lane_off >= 0) {
-                                const double *w = ptab + 2 * G.lane_off;
-                                f *= cd(w[2 * (tid & 63)], w[2 * (tid & 63) + 1]);
-                            }
+                        if (!on) continue;
+                        cd f(1, 0);
+                        if (G.uidx >= 0) f = ufac[G.uidx];
+                        if (G.wave_off >= 0) {
+                            const double *w = ptab + 2 * G.wave_off;
+                            f *= cd(w[2 * (tid >> 6)], w[2 * (tid >> 6) + 1]);
                         }
-                        // the planner promises the group covers every multiplied slot
-                        for (int k = 0; k < R; ++k)
-                            if (((rec->kmask >> k) & 1u) && (k & G.rmask) != G.rmask) return_error = true;
+                        if (G.lane_off >= 0) {
+                            const double *w = ptab + 2 * G.lane_off;
+                            f *= cd(w[2 * (tid & 63)], w[2 * (tid & 63) + 1]);
+                        }
+                        gf[i] = f;
                     }
                     for (int k = 0; k < R; ++k) {
                         if (!((rec->kmask >> k) & 1u)) continue;
-                        cd F = f;
+                        cd F(1, 0);
+                        for (int i = 0; i < rec->ngroups; ++i)
+                            if ((k & gs[i].rmask) == gs[i].rmask) F *= gf[i];
                         if ((rec->qmask >> k) & 1u) F *= cd(qt[2 * k], qt[2 * k + 1]);
                         a[tid][k] *= F;
                     }

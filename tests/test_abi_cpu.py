@@ -8,6 +8,7 @@
 - invariants of the other schedules.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -243,3 +244,47 @@ def test_precompile_without_device():
     sv.sv_jit_precompile(12, "c64", g, sv.schedule(block_qubits=10))
     with pytest.raises(sv.SvError):
         sv.sv_jit_precompile(12, "c64", W.gates_from_tuples([("H", 12, -1, 0.0)]), sv.schedule())
+
+
+def _fnv1a64(data: bytes, h: int = 0xcbf29ce484222325) -> int:
+    for c in data:
+        h ^= c
+        h = (h * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_jit_cache_key_covers_headers_and_options(tmp_path, monkeypatch):
+    """A compiled pass module on disk is named by its source and by a hash of
+    the embedded handler/argument headers and the compile options, so a
+    change to k2_device.h or k2_abi.h (e.g. the K2Args layout) never loads a
+    stale module."""
+    monkeypatch.setenv("SV_JIT_CACHE_DIR", str(tmp_path))
+    sv.sv_jit_precompile(12, "c64", W.qpe_gates(12, 0.3), sv.schedule(block_qubits=10))
+    files = [f for f in os.listdir(tmp_path) if f.endswith(".co")]
+    assert len(files) == 1
+    csrc = os.path.join(os.path.dirname(sv.__file__), "csrc")
+    abi = open(os.path.join(csrc, "k2_abi.h"), "rb").read()
+    dev = open(os.path.join(csrc, "k2_device.h"), "rb").read()
+    opts = [b"--offload-arch=gfx950", b"-O3", b"-std=c++17", b"-ffp-contract=off", b"-Xclang",
+            b"-target-feature", b"-Xclang", b"-packed-fp32-ops"]
+    want = _fnv1a64(b"\0".join([abi, dev] + opts))
+    assert files[0].endswith(f"-{want:016x}.co"), files[0]
+    # a one-byte change of the device header text changes the key
+    assert _fnv1a64(b"\0".join([abi, dev + b" "] + opts)) != want
+
+
+def test_oracle_float_build_tracks_the_fp64_oracle():
+    """The float build (timing only) computes the same circuit in binary32:
+    within complex64 rounding of the FP64 oracle, never bit-identical."""
+    from oracle import timing as T
+    n = 12
+    g = W.qpe_gates(n, 0.2718)
+    S = T.alloc_state(n, "f32")
+    T.time_gate_loop(n, g, S, "f32")
+    got = S[0::2].astype(np.float64) + 1j * S[1::2]
+    want = oracle.apply(n, g)
+    err = np.max(np.abs(got - want))
+    assert 0 < err < 2e-5
+    S64 = T.alloc_state(n, "f64")
+    T.time_gate_loop(n, g, S64, "f64")
+    assert np.array_equal(S64[0::2] + 1j * S64[1::2], want)
