@@ -263,6 +263,19 @@ sv_status sv_set_state_range(sv_handle h, uint64_t offset, uint64_t count, const
  * its argmax m (lowest index wins ties), phi = m / 2^t and P(m). */
 sv_status sv_qpe_readout(sv_handle h, int t, uint64_t *m, double *phi, double *pmax);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the QPE
+ * readout of sv_qpe_readout, same kernels and results, with no allocation of
+ * any kind. Its scratch (per-work-group partial maxima and the result) lives
+ * in a file-scope device array of 128 KiB + 256 bytes that each GPU holds
+ * until the process ends; every call on a GPU shares it and it keeps the last
+ * call's contents (nothing in it needs clearing: each call writes what it
+ * reads), so calls that overlap on one GPU (several streams or threads) race.
+ * Limit: n - t <= 4 (QPE has n - t = 1); a larger complement would need a
+ * marginal buffer beyond the array and returns SV_ERR_UNSUPPORTED. Host
+ * outputs; synchronizes the handle's stream. */
+sv_status sv_qpe_readout_noalloc(sv_handle h, int t, uint64_t *m, double *phi, double *pmax);
+
 /* Sum of |alpha|^2 in FP64. Also records |norm - 1| in the stats. */
 sv_status sv_norm(sv_handle h, double *norm2);
 

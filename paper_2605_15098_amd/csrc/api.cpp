@@ -759,6 +759,43 @@ sv_status sv_qpe_readout(sv_handle h, int t, uint64_t *m, double *phi, double *p
     return SV_OK;
 }
 
+sv_status sv_qpe_readout_noalloc(sv_handle h, int t, uint64_t *m, double *phi, double *pmax)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (t < 1 || t > h->n) return fail(SV_ERR_INVALID_ARG, "t out of range");
+    if (!m || !phi || !pmax) return fail(SV_ERR_INVALID_ARG, "null output");
+    if (h->n - t > 4)
+        return fail(SV_ERR_UNSUPPORTED, "allocation-free readout needs n - t <= 4 (the counting marginal of a state "
+                                        "with more than 4 other qubits needs a marginal buffer beyond the static "
+                                        "scratch)");
+    const size_t am = svk::argmax_scratch_bytes(1ull << t);
+    if (am + 16 > svk::static_scratch_bytes())
+        return fail(SV_ERR_UNSUPPORTED, "readout scratch larger than the static scratch");
+    // counting qubits' physical bits and the others, ascending (no host allocation)
+    int qb[64], ob[64], no = 0;
+    bool inq[64] = {};
+    for (int k = 0; k < t; ++k) {
+        qb[k] = h->l2p[k];
+        inq[qb[k]] = true;
+    }
+    for (int p = 0; p < h->n; ++p)
+        if (!inq[p]) ob[no++] = p;
+    void *base = nullptr;
+    SV_HIP(svk::static_scratch(&base), "hipGetSymbolAddress");
+    uint64_t *ri = (uint64_t *)((char *)base + am);
+    double *rv = (double *)((char *)base + am + 8);
+    SV_HIP(svk::marginal_argmax(h->buf, h->n, h->dtype, qb, t, ob, base, ri, rv, h->stream), "qpe readout");
+    uint64_t hi = 0;
+    double hv = 0;
+    SV_HIP(hipMemcpyAsync(&hi, ri, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+    SV_HIP(hipMemcpyAsync(&hv, rv, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+    SV_HIP(hipStreamSynchronize(h->stream), "sync");
+    *m = hi;
+    *pmax = hv;
+    *phi = std::ldexp((double)hi, -t);
+    return SV_OK;
+}
+
 static sv_status state_io(sv_handle h, uint64_t offset, uint64_t count, void *out, const void *in)
 {
     const uint64_t N = 1ull << h->n;

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "k2_device.h"
 #include "launch.h"
@@ -665,6 +666,35 @@ __global__ void __launch_bounds__(256) marg_argmax_stage1(const C *__restrict__ 
         }
     }
     block_argmax(bv, bi, nullptr, nullptr, &pv[blockIdx.x], &pi[blockIdx.x]);
+}
+
+// Scratch of the allocation-free readout: partial maxima of the fused
+// marginal/argmax kernels, then the result (index, value). One copy per GPU
+// for the life of the process; in host code the name below is not a device
+// address: kernels get the per-device address from static_scratch().
+constexpr size_t kStaticScratchBytes = (size_t)AM_BLOCKS * (sizeof(double) + sizeof(uint64_t)) + 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+hipError_t static_scratch(void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t marginal_argmax(const void *S, int n, int dtype, const int *qbits, int nq, const int *obits,

@@ -53,6 +53,12 @@ hipError_t argmax(const double *p, uint64_t len, void *scratch, uint64_t *res_id
 hipError_t marginal_argmax(const void *S, int n, int dtype, const int *qbits, int nq,
                            const int *obits, void *scratch, uint64_t *res_idx, double *res_val,
                            hipStream_t st);
+// Device scratch that is never allocated: a file-scope array of
+// static_scratch_bytes() per GPU, large enough for marginal_argmax's scratch
+// (argmax_scratch_bytes) plus 256 bytes of results. static_scratch() returns
+// its address on the current device (looked up once per device).
+size_t static_scratch_bytes();
+hipError_t static_scratch(void **out);
 size_t norm_scratch_bytes(int n);
 hipError_t norm2(const void *S, int n, int dtype, void *scratch, double *res, hipStream_t st);
 // Logical-order gather: out[i] = S[phys(offset + i)] for i < count.

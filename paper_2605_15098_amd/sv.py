@@ -120,6 +120,9 @@ _SIGS = {
     "sv_qpe_readout": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                        ctypes.c_int32),
+    "sv_qpe_readout_noalloc": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                               ctypes.c_int32),
     "sv_norm": ([_VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int32),
     "sv_stats_get": ([_VP, ctypes.POINTER(sv_stats)], ctypes.c_int32),
     "sv_plan": ([ctypes.c_int, ctypes.c_int, _VP, ctypes.c_size_t, ctypes.POINTER(sv_schedule),
@@ -311,6 +314,15 @@ def sv_qpe_readout(h, t: int):
     p = ctypes.c_double()
     _check(load().sv_qpe_readout(_VP(h), int(t), ctypes.byref(m), ctypes.byref(phi),
                                  ctypes.byref(p)))
+    return int(m.value), float(phi.value), float(p.value)
+
+
+def sv_qpe_readout_noalloc(h, t: int):
+    m = ctypes.c_uint64()
+    phi = ctypes.c_double()
+    p = ctypes.c_double()
+    _check(load().sv_qpe_readout_noalloc(_VP(h), int(t), ctypes.byref(m), ctypes.byref(phi),
+                                         ctypes.byref(p)))
     return int(m.value), float(phi.value), float(p.value)
 
 
