@@ -192,7 +192,13 @@ sv_status sv_create(int n, sv_dtype dtype, sv_handle *out);
 /* Borrow a device buffer (e.g. a torch tensor's storage) of at least
  * 2^n * sizeof(amplitude) bytes and a HIP stream (NULL = default stream).
  * The buffer's content is taken as the state in logical order; it is not
- * cleared. The caller keeps buffer and stream alive until sv_destroy. */
+ * cleared. The caller keeps buffer and stream alive until sv_destroy.
+ * While wrapped (and after sv_destroy) the buffer holds the amplitudes in
+ * the library's storage order: the qubit layout (sv_layout) and, from 2^15
+ * amplitudes (complex64) or 2^14 (complex128) on, a fixed GF(2)-linear
+ * permutation of the index that spreads block-pass accesses over the HBM
+ * channels; sv_wrap reorders the buffer in place once (one pass) and
+ * readouts always return logical order. */
 sv_status sv_wrap(int n, sv_dtype dtype, void *dev_buf, size_t bytes, void *hip_stream,
                   sv_handle *out);
 

@@ -503,6 +503,12 @@ sv_status sv_wrap(int n, sv_dtype dtype, void *dev_buf, size_t bytes, void *hip_
     h->bytes = bytes;
     h->owns = false;
     h->stream = (hipStream_t)hip_stream;
+    // the buffer holds the state in logical order: bring it to storage order
+    hipError_t e = svk::to_storage_order(h->buf, n, dtype, h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "storage order");
+    }
     return finish_handle(h, out);
 }
 
@@ -804,7 +810,8 @@ static sv_status state_io(sv_handle h, uint64_t offset, uint64_t count, void *ou
     const size_t ab = amp_bytes(h->dtype);
     void *user = out ? out : const_cast<void *>(in);
     const bool dev = is_device_ptr(user);
-    const bool ident = identity(h->l2p);
+    // a plain copy only where the physical layout and the storage order are both the identity
+    const bool ident = identity(h->l2p) && svk::plain_storage(h->n, h->dtype);
     char *sbase = (char *)h->buf + offset * ab;
     if (ident) {
         if (out) {

@@ -81,6 +81,23 @@ __device__ __forceinline__ uint32_t insert0_32(uint32_t x, int b)
     return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u));
 }
 
+// Storage order of the state in HBM: amplitude i (physical index, after the
+// qubit layout) is kept at sto(i), which XORs index bits S0 .. S0+8 (byte
+// address bits 8..16: S0 = 5 for complex64, 4 for complex128) with a fold of
+// the bits above them. A block whose local bits are the low S0 bits plus
+// high bits (the block pass's scattered runs) then spreads its runs over
+// the HBM channels instead of drawing them all from the few that its fixed
+// middle address bits select; runs of 2^S0 amplitudes and aligned ranges of
+// 2^(S0+9) amplitudes stay contiguous. The map is linear over GF(2)
+// (sto(x ^ y) = sto(x) ^ sto(y)) and is its own inverse; states below
+// 2^(S0+10) amplitudes are stored in plain order.
+template <typename C> __host__ __device__ __forceinline__ uint64_t sto(uint64_t i)
+{
+    constexpr int S0 = sizeof(C) == 8 ? 5 : 4;
+    const uint64_t h = i >> (S0 + 9);
+    return i ^ (((h ^ (h >> 9) ^ (h >> 18) ^ (h >> 27) ^ (h >> 36)) & 511ull) << S0);
+}
+
 // LDS index swizzle: the low bits that span one 128-byte bank row are XORed
 // with a fold of the higher bits, so lanes whose local indices differ only in
 // high bits still spread over the banks. The map is linear over GF(2) (shifts,
@@ -558,18 +575,21 @@ __device__ __forceinline__ uint64_t k2_deposit(uint64_t v, uint64_t mask)
     return out;
 }
 
+// Register slot k of the thread is amplitude tbase ^ (XOR of roff[j] over
+// the set bits j of k): tbase and roff are already in storage order (sto is
+// linear), so the storage order costs nothing per access.
 template <int LOGR, typename C>
-__device__ __forceinline__ void k2_load(C *a, const C *__restrict__ S, uint64_t tmem, const uint64_t *roff, bool vec2)
+__device__ __forceinline__ void k2_load(C *a, const C *__restrict__ S, uint64_t tbase, const uint64_t *roff, bool vec2)
 {
     constexpr int R = 1 << LOGR;
     if (sizeof(C) == 8 && vec2) {
         // memory bit 0 is local bit 0 = slot 0: slots k, k+1 are adjacent
 #pragma unroll
         for (int k = 0; k < R; k += 2) {
-            uint64_t addr = tmem;
+            uint64_t addr = tbase;
 #pragma unroll
             for (int j = 1; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
+                if ((k >> j) & 1) addr ^= roff[j];
             const float4 v = *reinterpret_cast<const float4 *>(S + addr);
             a[k] = mk<C>(v.x, v.y);
             a[k + 1] = mk<C>(v.z, v.w);
@@ -577,26 +597,26 @@ __device__ __forceinline__ void k2_load(C *a, const C *__restrict__ S, uint64_t 
     } else {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            uint64_t addr = tmem;
+            uint64_t addr = tbase;
 #pragma unroll
             for (int j = 0; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
+                if ((k >> j) & 1) addr ^= roff[j];
             a[k] = S[addr];
         }
     }
 }
 
 template <int LOGR, typename C>
-__device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t tmem, const uint64_t *roff, bool vec2)
+__device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t tbase, const uint64_t *roff, bool vec2)
 {
     constexpr int R = 1 << LOGR;
     if (sizeof(C) == 8 && vec2) {
 #pragma unroll
         for (int k = 0; k < R; k += 2) {
-            uint64_t addr = tmem;
+            uint64_t addr = tbase;
 #pragma unroll
             for (int j = 1; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
+                if ((k >> j) & 1) addr ^= roff[j];
             float4 v;
             v.x = (float)a[k].x;
             v.y = (float)a[k].y;
@@ -607,10 +627,10 @@ __device__ __forceinline__ void k2_store(const C *a, C *__restrict__ S, uint64_t
     } else {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            uint64_t addr = tmem;
+            uint64_t addr = tbase;
 #pragma unroll
             for (int j = 0; j < LOGR; ++j)
-                if ((k >> j) & 1) addr += roff[j];
+                if ((k >> j) & 1) addr ^= roff[j];
             S[addr] = a[k];
         }
     }
@@ -676,10 +696,11 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         tmem_local |= (uint64_t)((tid >> c) & 1u) << args.bits[i];
         ++c;
     }
+    tmem_local = sto<C>(tmem_local);
     // (read as wave-uniform values: they stay in scalar registers)
     uint64_t roff[LOGR];
 #pragma unroll
-    for (int j = 0; j < LOGR; ++j) roff[j] = uniform64(1ull << args.bits[svp::k2_canon_bit(j, l, LOGR)]);
+    for (int j = 0; j < LOGR; ++j) roff[j] = uniform64(sto<C>(1ull << args.bits[svp::k2_canon_bit(j, l, LOGR)]));
 
     uint64_t bid = first;
     if (bid >= nblocks) return;
@@ -698,7 +719,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
     }
     uint64_t base = uniform64(k2_deposit(bid, gmask) | base_or);
     C a[R], b[PF ? R : 1];
-    k2_load<LOGR>(a, S, base | tmem_local, roff, vec2);
+    k2_load<LOGR>(a, S, sto<C>(base) ^ tmem_local, roff, vec2);
 
     for (;;) {
         const uint64_t next = bid + stride;
@@ -707,7 +728,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         // this block's data does not also wait for the prefetch.
         const uint64_t nbase = has_next ? uniform64(k2_deposit(next, gmask) | base_or) : base;
         if constexpr (PF > 0)
-            if (PF == 2 || has_next) k2_load<LOGR>(b, S, nbase | tmem_local, roff, vec2);
+            if (PF == 2 || has_next) k2_load<LOGR>(b, S, sto<C>(nbase) ^ tmem_local, roff, vec2);
 
         // Block-uniform phase factors of the diagonal runs: each is
         // e^{2 pi i sum angle_j [base covers tmask_j]}, summed exactly in
@@ -753,7 +774,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         // keeping the load's live across the program (dozens of registers).
         uint64_t tm_st = tmem_local;
         asm volatile("" : "+v"(tm_st));
-        k2_store<LOGR>(a, S, base | tm_st, roff, vec2);
+        k2_store<LOGR>(a, S, sto<C>(base) ^ tm_st, roff, vec2);
         if (!has_next) break;
         if (args.nug > 0) lds_barrier();  // the next block's factors overwrite ufac
         if constexpr (PF > 0) {
@@ -762,7 +783,7 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
         } else {
             uint64_t tm_ld = tmem_local;
             asm volatile("" : "+v"(tm_ld));
-            k2_load<LOGR>(a, S, nbase | tm_ld, roff, vec2);
+            k2_load<LOGR>(a, S, sto<C>(nbase) ^ tm_ld, roff, vec2);
         }
         base = nbase;
         bid = next;

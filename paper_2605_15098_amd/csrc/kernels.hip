@@ -59,6 +59,33 @@ hipError_t init_zero_state(void *S, int n, int dtype, hipStream_t st)
     return hipGetLastError();
 }
 
+// Logical-to-storage order in place (sto is its own inverse, so each pair
+// {i, sto(i)} is swapped once, by the thread of the smaller index).
+template <typename C> __global__ void __launch_bounds__(256) sto_inplace_kernel(C *S, uint64_t N)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        const uint64_t j = sto<C>(i);
+        if (j <= i) continue;
+        const C a = S[i];
+        S[i] = S[j];
+        S[j] = a;
+    }
+}
+
+hipError_t to_storage_order(void *S, int n, int dtype, hipStream_t st)
+{
+    const uint64_t N = 1ull << n;
+    const int s0 = dtype == 0 ? 5 : 4;
+    if (n < s0 + 10) return hipSuccess;  // stored in plain order
+    const unsigned g = grid_for(N, 256, 8192);
+    if (dtype == 0) sto_inplace_kernel<float2><<<g, 256, 0, st>>>((float2 *)S, N);
+    else sto_inplace_kernel<double2><<<g, 256, 0, st>>>((double2 *)S, N);
+    return hipGetLastError();
+}
+
+bool plain_storage(int n, int dtype) { return n < (dtype == 0 ? 5 : 4) + 10; }
+
 // ---------------------------------------------------------------- k1
 
 constexpr int K1_BLOCK = 256;
@@ -83,17 +110,19 @@ k1_pair_kernel(C *__restrict__ S, uint64_t npairs, int t, int c, int kind, C u00
         uint64_t j = insert0(p, lo);
         if (c >= 0) j = insert0(j, hi);
         j |= cbit;
-        C a = S[j], b = S[j + h];
+        // storage order: sto(j + h) = sto(j) ^ sto(h), bit t of j being clear
+        const uint64_t sj = sto<C>(j), sk = sj ^ sto<C>(h);
+        C a = S[sj], b = S[sk];
         if (kind == K1_H) {
             hbfly(a, b);
-            S[j] = a;
-            S[j + h] = b;
+            S[sj] = a;
+            S[sk] = b;
         } else if (kind == K1_X) {
-            S[j] = b;
-            S[j + h] = a;
+            S[sj] = b;
+            S[sk] = a;
         } else {
-            S[j] = cmad2(u00, a, u01, b);
-            S[j + h] = cmad2(u10, a, u11, b);
+            S[sj] = cmad2(u00, a, u01, b);
+            S[sk] = cmad2(u10, a, u11, b);
         }
     }
 }
@@ -117,9 +146,10 @@ k1_diag_kernel(C *__restrict__ S, uint64_t namps, int nones, int lo, int hi, int
         if (nones >= 1) j = insert0(j, lo);
         if (nones >= 2) j = insert0(j, hi);
         j |= ones;
-        C a = S[j];
+        const uint64_t sj = sto<C>(j);
+        C a = S[sj];
         const C d = csel(tsel >= 0 && !((j >> tsel) & 1ull), d0, d1);
-        S[j] = cmul(d, a);
+        S[sj] = cmul(d, a);
     }
 }
 
@@ -170,10 +200,10 @@ __global__ void __launch_bounds__(K1_BLOCK) k3_kernel(C *__restrict__ S, uint64_
         const uint64_t q = base + (uint64_t)i * K1_BLOCK;
         if (q >= npairs) break;
         uint64_t j = insert0(insert0(q, lo), hi) | (1ull << p);
-        const uint64_t k = j ^ flip;
-        C a = S[j], b = S[k];
-        S[j] = b;
-        S[k] = a;
+        const uint64_t sj = sto<C>(j), sk = sto<C>(j ^ flip);
+        C a = S[sj], b = S[sk];
+        S[sj] = b;
+        S[sk] = a;
     }
 }
 
@@ -438,7 +468,7 @@ probs_kernel(const C *__restrict__ S, PermArg pa, double *__restrict__ out, uint
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
-        out[i] = prob(S[phys_of(off + i, pa)]);
+        out[i] = prob(S[sto<C>(phys_of(off + i, pa))]);
 }
 
 hipError_t probabilities(const void *S, int n, int dtype, const int *perm, double *out,
@@ -476,7 +506,7 @@ marg_direct_kernel(const C *__restrict__ S, BitList qb, BitList ob, double *__re
     for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += stride) {
         const uint64_t bm = deposit(m, qb);
         double s = 0.0;
-        for (uint64_t o = 0; o < O; ++o) s += prob(S[bm | deposit(o, ob)]);
+        for (uint64_t o = 0; o < O; ++o) s += prob(S[sto<C>(bm | deposit(o, ob))]);
         out[m] = s;
     }
 }
@@ -498,7 +528,7 @@ marg_chunk_kernel(const C *__restrict__ S, BitList qb, BitList ob, double *__res
     if (o1 > O) o1 = O;
     const uint64_t bm = deposit(m, qb);
     double s = 0.0;
-    for (uint64_t o = o0 + threadIdx.x; o < o1; o += blockDim.x) s += prob(S[bm | deposit(o, ob)]);
+    for (uint64_t o = o0 + threadIdx.x; o < o1; o += blockDim.x) s += prob(S[sto<C>(bm | deposit(o, ob))]);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -658,7 +688,7 @@ __global__ void __launch_bounds__(256) marg_argmax_stage1(const C *__restrict__ 
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += stride) {
         const uint64_t bm = deposit_runs(p, qm);
         double s = 0.0;
-        for (uint64_t o = 0; o < O; ++o) s += prob(S[bm | deposit(o, ob)]);
+        for (uint64_t o = 0; o < O; ++o) s += prob(S[sto<C>(bm | deposit(o, ob))]);
         if (s >= bv) {
             uint64_t m = 0;
             for (int k = 0; k < qm.cnt; ++k) m |= ((p >> k) & 1ull) << qm.lbit[k];
@@ -783,7 +813,7 @@ __global__ void __launch_bounds__(256) gather_kernel(const C *__restrict__ S, Pe
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
-        out[i] = S[phys_of(off + i, pa)];
+        out[i] = S[sto<C>(phys_of(off + i, pa))];
 }
 
 template <typename C>
@@ -792,7 +822,7 @@ __global__ void __launch_bounds__(256) scatter_kernel(C *__restrict__ S, PermArg
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
-        S[phys_of(off + i, pa)] = in[i];
+        S[sto<C>(phys_of(off + i, pa))] = in[i];
 }
 
 hipError_t gather_logical(const void *S, int n, int dtype, const int *perm, void *out, uint64_t offset,

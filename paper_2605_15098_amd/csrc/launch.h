@@ -14,6 +14,11 @@ namespace svk {
 using K2Args = svp::K2Args;
 
 hipError_t init_zero_state(void *S, int n, int dtype, hipStream_t st);
+// The state's storage order (sto in k2_device.h): every kernel addresses
+// amplitude i at sto(i). plain_storage: the order is the identity for this
+// size. to_storage_order: reorder a buffer given in plain order, in place.
+bool plain_storage(int n, int dtype);
+hipError_t to_storage_order(void *S, int n, int dtype, hipStream_t st);
 
 // Batched passes: see k6_batch_kernel. grid must not exceed the resident
 // capacity (k6_occupancy work-groups per CU times the CU count) so that the
