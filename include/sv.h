@@ -269,6 +269,25 @@ sv_status sv_set_state_range(sv_handle h, uint64_t offset, uint64_t count, const
  * its argmax m (lowest index wins ties), phi = m / 2^t and P(m). */
 sv_status sv_qpe_readout(sv_handle h, int t, uint64_t *m, double *phi, double *pmax);
 
+/* ---- measurement (the meters of the QPE figure, Section IV-A) ----
+ * The outcome of measuring qubits[0..nq-1] (nq = 0: all n qubits in order)
+ * is the integer m whose bit k is the value of qubit qubits[k], drawn with
+ * its Born probability P(m) (FP64). Random numbers are the caller's: each
+ * uniform u in [0, 1) maps to the smallest m with C(m) > u * C(2^nq - 1),
+ * C(m) = P(0) + ... + P(m) (inverse CDF over ascending m, summed in FP64 in
+ * a fixed order; dividing by the total keeps a drifted norm harmless). At
+ * most 32 measured qubits; 2^nq doubles of device scratch. */
+
+/* `shots` outcomes for the uniforms (host or device arrays, shots each);
+ * the state is unchanged. */
+sv_status sv_sample(sv_handle h, const int *qubits, int nq, const double *uniforms, size_t shots, uint64_t *out);
+
+/* One projective measurement with the uniform u: draws m as above, then
+ * zeroes every amplitude whose measured qubits differ from m and scales the
+ * rest by 1/sqrt(P(m)) (collapse and renormalisation, one pass). Returns m
+ * and P(m) on the host. */
+sv_status sv_measure(sv_handle h, const int *qubits, int nq, double u, uint64_t *outcome, double *prob);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the QPE
  * readout of sv_qpe_readout, same kernels and results, with no allocation of

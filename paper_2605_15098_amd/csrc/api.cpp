@@ -765,6 +765,118 @@ sv_status sv_qpe_readout(sv_handle h, int t, uint64_t *m, double *phi, double *p
     return SV_OK;
 }
 
+// Outcome probabilities of the listed qubits (all qubits in order when
+// nq = 0) into device memory at dst (2^nq doubles, or 2^n); work is device
+// scratch of outcome_work_bytes.
+static size_t outcome_work_bytes(sv_handle h, int nq)
+{
+    return nq == 0 ? 0 : svk::marginal_scratch_bytes(h->n, nq);
+}
+
+static sv_status outcome_probs(sv_handle h, const int *qubits, int nq, double *dst, void *work)
+{
+    if (nq == 0) {
+        SV_HIP(svk::probabilities(h->buf, h->n, h->dtype, h->l2p.data(), dst, 0, 1ull << h->n, h->stream), "probs");
+        return SV_OK;
+    }
+    std::vector<int> qb;
+    for (int k = 0; k < nq; ++k) qb.push_back(h->l2p[qubits[k]]);
+    const std::vector<int> ob = complement(h->n, qb);
+    SV_HIP(svk::marginal(h->buf, h->n, h->dtype, qb.data(), nq, ob.data(), dst, work, h->stream), "marginal");
+    return SV_OK;
+}
+
+static sv_status check_measured(sv_handle h, const int *qubits, int nq)
+{
+    if (nq < 0 || nq > h->n) return fail(SV_ERR_INVALID_ARG, "nq out of range");
+    if (nq > 0 && !qubits) return fail(SV_ERR_INVALID_ARG, "qubits is null");
+    std::vector<bool> seen(h->n, false);
+    for (int k = 0; k < nq; ++k) {
+        if (qubits[k] < 0 || qubits[k] >= h->n || seen[qubits[k]])
+            return fail(SV_ERR_INVALID_ARG, "qubit list has an out-of-range or repeated entry");
+        seen[qubits[k]] = true;
+    }
+    const int m = nq == 0 ? h->n : nq;
+    if (m > 32) return fail(SV_ERR_UNSUPPORTED, "more than 32 measured qubits");
+    if (nq > 0 && h->n - nq > 12 && nq > 16) return fail(SV_ERR_UNSUPPORTED, "marginal shape not supported");
+    return SV_OK;
+}
+
+sv_status sv_sample(sv_handle h, const int *qubits, int nq, const double *uniforms, size_t shots, uint64_t *out)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (sv_status s = check_measured(h, qubits, nq)) return s;
+    if (shots > 0 && (!uniforms || !out)) return fail(SV_ERR_INVALID_ARG, "null uniforms or output");
+    if (shots == 0) return SV_OK;
+    const bool du = is_device_ptr(uniforms), dout = is_device_ptr(out);
+    const uint64_t M = 1ull << (nq == 0 ? h->n : nq);
+    const size_t chunk = std::min<size_t>(shots, size_t(1) << 22);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t o_p = 0, o_c = up(M * 8), o_w = o_c + up(M * 8);
+    const size_t o_u = o_w + up(std::max(outcome_work_bytes(h, nq), svk::scan_scratch_bytes(M)));
+    const size_t o_o = o_u + up(chunk * 8), need = o_o + up(chunk * 8);
+    if (sv_status st = ensure_scratch(h, need)) return st;
+    char *base = (char *)h->scratch;
+    double *P = (double *)(base + o_p), *cdf = (double *)(base + o_c);
+    if (sv_status st = outcome_probs(h, qubits, nq, P, base + o_w)) return st;
+    SV_HIP(svk::scan_inclusive(P, cdf, M, base + o_w, h->stream), "scan");
+    for (size_t off = 0; off < shots; off += chunk) {
+        const size_t c = std::min(chunk, shots - off);
+        const double *u = uniforms + off;
+        if (!du) {
+            SV_HIP(hipMemcpyAsync(base + o_u, u, c * 8, hipMemcpyHostToDevice, h->stream), "copy");
+            u = (const double *)(base + o_u);
+        }
+        uint64_t *o = dout ? out + off : (uint64_t *)(base + o_o);
+        SV_HIP(svk::sample_outcomes(cdf, M, u, c, o, h->stream), "sample");
+        if (!dout) {
+            SV_HIP(hipMemcpyAsync(out + off, o, c * 8, hipMemcpyDeviceToHost, h->stream), "copy");
+            SV_HIP(hipStreamSynchronize(h->stream), "sync");
+        }
+    }
+    return SV_OK;
+}
+
+sv_status sv_measure(sv_handle h, const int *qubits, int nq, double u, uint64_t *outcome, double *prob)
+{
+    if (sv_status s = check_handle(h)) return s;
+    if (sv_status s = check_measured(h, qubits, nq)) return s;
+    if (!outcome || !prob) return fail(SV_ERR_INVALID_ARG, "null output");
+    if (!(u >= 0.0 && u < 1.0)) return fail(SV_ERR_INVALID_ARG, "u must be in [0, 1)");
+    const uint64_t M = 1ull << (nq == 0 ? h->n : nq);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t o_p = 0, o_c = up(M * 8), o_w = o_c + up(M * 8);
+    const size_t o_u = o_w + up(std::max(outcome_work_bytes(h, nq), svk::scan_scratch_bytes(M)));
+    const size_t need = o_u + 256;
+    if (sv_status st = ensure_scratch(h, need)) return st;
+    char *base = (char *)h->scratch;
+    double *P = (double *)(base + o_p), *cdf = (double *)(base + o_c);
+    if (sv_status st = outcome_probs(h, qubits, nq, P, base + o_w)) return st;
+    SV_HIP(svk::scan_inclusive(P, cdf, M, base + o_w, h->stream), "scan");
+    SV_HIP(hipMemcpyAsync(base + o_u, &u, 8, hipMemcpyHostToDevice, h->stream), "copy");
+    uint64_t *dm = (uint64_t *)(base + o_u + 64);
+    SV_HIP(svk::sample_outcomes(cdf, M, (const double *)(base + o_u), 1, dm, h->stream), "sample");
+    uint64_t m = 0;
+    SV_HIP(hipMemcpyAsync(&m, dm, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+    SV_HIP(hipStreamSynchronize(h->stream), "sync");
+    double pm = 0.0;
+    SV_HIP(hipMemcpyAsync(&pm, P + m, 8, hipMemcpyDeviceToHost, h->stream), "copy");
+    SV_HIP(hipStreamSynchronize(h->stream), "sync");
+    if (!(pm > 0.0)) return fail(SV_ERR_INVALID_ARG, "the drawn outcome has zero probability (state is zero)");
+    // the measured qubits' physical bits must equal m's bits
+    uint64_t mask = 0, val = 0;
+    const int cnt = nq == 0 ? h->n : nq;
+    for (int k = 0; k < cnt; ++k) {
+        const int pb = h->l2p[nq == 0 ? k : qubits[k]];
+        mask |= 1ull << pb;
+        if ((m >> k) & 1ull) val |= 1ull << pb;
+    }
+    SV_HIP(svk::collapse(h->buf, h->n, h->dtype, mask, val, 1.0 / std::sqrt(pm), h->stream), "collapse");
+    *outcome = m;
+    *prob = pm;
+    return SV_OK;
+}
+
 sv_status sv_qpe_readout_noalloc(sv_handle h, int t, uint64_t *m, double *phi, double *pmax)
 {
     if (sv_status s = check_handle(h)) return s;

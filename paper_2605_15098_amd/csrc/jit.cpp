@@ -179,11 +179,15 @@ static std::string generate_pass(const svp::Step &s, const svp::Plan &plan, int 
     // prefetched (the other work-group computes while one waits). The others
     // prefetch into a second register set.
     const bool two = s.half_lds && threads * 2 <= 1024;
+    // a pass with matrix-core windows keeps no prefetch set either: the
+    // windows' operands and accumulators take those registers
+    bool windows = false;
+    for (int i = 0; i < s.op_count; ++i) windows = windows || plan.ops[s.op_begin + i].kind == svp::K2_MFMA;
     o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ")";
     if (two) o << " __attribute__((amdgpu_waves_per_eu(" << (threads / 64 * 2 + 3) / 4 << ")))";
     o << " svk2_pass_" << idx << "(CT<" << T << ">::type *__restrict__ S, svp::K2Args args) {\n"
       << "  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[" << (lds > 0 ? lds : 16) << "];\n"
-      << "  k2_body<" << T << ", " << r << ", " << (vec2 ? "true" : "false") << ", " << (two ? 0 : 2)
+      << "  k2_body<" << T << ", " << r << ", " << (vec2 ? "true" : "false") << ", " << (two || windows ? 0 : 2)
       << ">(S, args, lds_raw, Prog" << idx << "{}, blockIdx.x, gridDim.x);\n}\n";
     return o.str();
 }

@@ -83,7 +83,9 @@ struct DiagRun {
 };
 
 // Block-uniform factor: e^{2 pi i sum angle_j [base covers tmask_j]} with
-// angles as 64-bit fixed-point turns; computed once per block.
+// angles as 64-bit fixed-point turns; computed once per block (complex64:
+// from the exact sum of the angles; complex128: as the product of the
+// covered terms' factors re + i im, formed in binary64 on the host).
 struct UGroup {
     int32_t term_off;   // index of the group's first term in the pass's UTerm array
     int32_t nterms;
@@ -91,6 +93,7 @@ struct UGroup {
 struct UTerm {
     uint64_t tmask;
     uint64_t angle;
+    double re, im;      // e^{2 pi i angle}
 };
 
 // Arguments of one block pass, passed by value.
@@ -135,7 +138,7 @@ inline K2Lds k2_lds_layout(int l, int amp, int nug, int tab_count, int nut, int 
     o.ufac = up(((uint32_t)amp << l) >> (half_lds ? 1 : 0));
     o.tabs = up(o.ufac + 16u * (uint32_t)nug);
     o.uterm = up(o.tabs + (uint32_t)amp * (uint32_t)tab_count);
-    o.ugrp = up(o.uterm + 16u * (uint32_t)nut);
+    o.ugrp = up(o.uterm + 32u * (uint32_t)nut);
     o.total = up(o.ugrp + 8u * (uint32_t)nug);
     return o;
 }

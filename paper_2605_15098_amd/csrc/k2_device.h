@@ -386,6 +386,20 @@ __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const in
     const uint32_t nvec = 1u << (l - KW);
     const int groups = (int)((nvec + 15u) >> 4);
     const T *M = static_cast<const T *>(mat);
+    // The table address is laundered so that its loads stay inside this op:
+    // they do not depend on the block, and hoisting every window's operands
+    // out of the block loop would need hundreds of registers.
+    asm volatile("" : "+s"(M));
+    // The lane's A operand for every (tile, step) of a 4-qubit window is
+    // loaded once per op (16 or 32 registers) while the block's own registers
+    // are parked in LDS; a 5-qubit window would take 64 or 128 registers, so
+    // its steps read the table, which stays in the caches.
+    constexpr bool AREG = KW == 4;
+    T areg[AREG ? TILES * STEPS : 1];
+    if constexpr (AREG) {
+#pragma unroll
+        for (int i = 0; i < TILES * STEPS; ++i) areg[i] = M[i * 64 + lane];
+    }
     // input element of lane: amplitude j = 2 s + (q >> 1), component q & 1
     const uint32_t in_lane = (q >> 1) ? wsw[0] : 0u;
     for (int g = wave; g < groups; g += nwaves) {
@@ -410,7 +424,12 @@ __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const in
             const T *src = reinterpret_cast<const T *>(cx.lds + (vsw ^ jsw) * (uint32_t)sizeof(C));
             const T bv = valid ? src[q & 1] : T(0);
 #pragma unroll
-            for (int t = 0; t < TILES; ++t) acc[t] = K2Mfma<T>::mma(M[(t * STEPS + s) * 64 + lane], bv, acc[t]);
+            for (int t = 0; t < TILES; ++t) {
+                T av;
+                if constexpr (AREG) av = areg[t * STEPS + s];
+                else av = M[(t * STEPS + s) * 64 + lane];
+                acc[t] = K2Mfma<T>::mma(av, bv, acc[t]);
+            }
         }
         if (valid) {
 #pragma unroll
@@ -737,19 +756,23 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
             const int gtid = (int)((wave_no << 6) | __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
             for (int g = gtid; g < args.nug; g += blockDim.x) {
                 const svp::UTerm *tm = uterm + ugrp[g].term_off;
-                uint64_t acc = 0;
-                for (int j = 0; j < ugrp[g].nterms; ++j)
-                    if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
                 if constexpr (sizeof(T) == 4) {
                     // complex64: the factor is rounded to FP32 anyway; the
-                    // top 32 bits of the turn count give it to 2^-31 half-turns
+                    // exact sum of the turns, its top 32 bits to 2^-31
+                    // half-turns, one FP32 sincospi
+                    uint64_t acc = 0;
+                    for (int j = 0; j < ugrp[g].nterms; ++j)
+                        if ((base & tm[j].tmask) == tm[j].tmask) acc += tm[j].angle;
                     float sn, cs;
                     sincospif(ldexpf((float)(int32_t)(acc >> 32), -31), &sn, &cs);
                     ufac[g] = make_double2(cs, sn);
                 } else {
-                    double sn, cs;
-                    sincospi(ldexp((double)(int64_t)acc, -63), &sn, &cs);
-                    ufac[g] = make_double2(cs, sn);
+                    // complex128: product of the covered terms' FP64
+                    // factors (no transcendental in the block loop)
+                    double2 f = make_double2(1.0, 0.0);
+                    for (int j = 0; j < ugrp[g].nterms; ++j)
+                        if ((base & tm[j].tmask) == tm[j].tmask) f = cmul(f, make_double2(tm[j].re, tm[j].im));
+                    ufac[g] = f;
                 }
             }
             lds_barrier();
@@ -791,12 +814,12 @@ __device__ __forceinline__ void k2_body(typename CT<T>::type *__restrict__ S, co
 }
 
 // k2_body with the access width chosen once, outside the block loop.
-template <typename T, int LOGR, class Prog>
+template <typename T, int LOGR, class Prog, int PF = 1>
 __device__ __forceinline__ void k2_body_any(typename CT<T>::type *__restrict__ S, const svp::K2Args &args,
                                             unsigned char *lds, const Prog &prog, uint64_t first, uint64_t stride)
 {
-    if (args.vec2) k2_body<T, LOGR, true, 1>(S, args, lds, prog, first, stride);
-    else k2_body<T, LOGR, false, 1>(S, args, lds, prog, first, stride);
+    if (args.vec2) k2_body<T, LOGR, true, PF>(S, args, lds, prog, first, stride);
+    else k2_body<T, LOGR, false, PF>(S, args, lds, prog, first, stride);
 }
 
 // ------------------------------------------------------------ interpreter

@@ -225,7 +225,9 @@ __global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
 k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ ops, svp::K2Args args)
 {
     extern __shared__ unsigned char lds_raw[];
-    k2_body_any<T, LOGR>(S, args, lds_raw, K2Interp<MFMA>{ops, args.nops, args.l}, blockIdx.x, gridDim.x);
+    // the build with matrix-core windows keeps no prefetch set (registers)
+    k2_body_any<T, LOGR, K2Interp<MFMA>, MFMA ? 0 : 1>(S, args, lds_raw, K2Interp<MFMA>{ops, args.nops, args.l},
+                                                        blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- k6
@@ -274,8 +276,9 @@ k6_batch_kernel(const svp::BatchInst *__restrict__ insts, const int32_t *__restr
     const uint64_t rank = blockIdx.x - I.group_off;
     for (int p = 0; p < I.npass; ++p) {
         const svp::BatchPass &P = passes[I.pass_off + p];
-        k2_body_any<T, LOGR>((C *)I.S, P.args, lds_raw, K2Interp<MFMA>{ops + P.op_begin, P.args.nops, P.args.l}, rank,
-                         (uint64_t)I.group_size);
+        k2_body_any<T, LOGR, K2Interp<MFMA>, MFMA ? 0 : 1>((C *)I.S, P.args, lds_raw,
+                                                            K2Interp<MFMA>{ops + P.op_begin, P.args.nops, P.args.l},
+                                                            rank, (uint64_t)I.group_size);
         if (I.group_size > 1 && p + 1 < I.npass)
             if (!group_barrier(&ctrs[I.ctr], (unsigned)((p + 1) * I.group_size), err, limit, &ok)) return;
     }
@@ -380,6 +383,140 @@ hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const s
                           : k2_dispatch<double, true>(S, logr, a, ops, st);
     return dtype == 0 ? k2_dispatch<float, false>(S, logr, a, ops, st)
                       : k2_dispatch<double, false>(S, logr, a, ops, st);
+}
+
+// ---------------------------------------------------------------- measurement
+
+// Inclusive prefix sums of FP64 values in a fixed order (deterministic):
+// tiles of SCAN_TILE values, each thread summing SCAN_PER consecutive values,
+// a work-group scan of the thread sums, then the tiles' totals scanned the
+// same way (recursively) and added back.
+constexpr int SCAN_THREADS = 256, SCAN_PER = 8, SCAN_TILE = SCAN_THREADS * SCAN_PER;
+
+__device__ double block_exclusive_scan(double v, double *sh, double *total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < SCAN_THREADS; d <<= 1) {
+        const double x = t >= d ? sh[t - d] : 0.0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    const double incl = sh[t];
+    *total = sh[SCAN_THREADS - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) scan_tiles(const double *__restrict__ in, double *__restrict__ out,
+                                                            uint64_t m, double *__restrict__ tile_sums)
+{
+    __shared__ double sh[SCAN_THREADS];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER;
+    double v[SCAN_PER], s = 0.0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) {
+        v[k] = base + k < m ? in[base + k] : 0.0;
+        s += v[k];
+        v[k] = s;
+    }
+    double total;
+    const double off = block_exclusive_scan(s, sh, &total);
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k)
+        if (base + k < m) out[base + k] = off + v[k];
+    if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) scan_add(double *__restrict__ out, uint64_t m,
+                                                          const double *__restrict__ tile_incl)
+{
+    if (blockIdx.x == 0) return;
+    const double off = tile_incl[blockIdx.x - 1];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k)
+        if (base + k < m) out[base + k] += off;
+}
+
+size_t scan_scratch_bytes(uint64_t m)
+{
+    size_t b = 0;
+    for (uint64_t x = (m + SCAN_TILE - 1) / SCAN_TILE; x > 1; x = (x + SCAN_TILE - 1) / SCAN_TILE) b += x * 8;
+    return b + 64;
+}
+
+hipError_t scan_inclusive(const double *in, double *out, uint64_t m, void *scratch, hipStream_t st)
+{
+    const uint64_t tiles = (m + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles > 0xffffffffull) return hipErrorInvalidValue;
+    double *sums = tiles > 1 ? (double *)scratch : nullptr;
+    scan_tiles<<<(unsigned)tiles, SCAN_THREADS, 0, st>>>(in, out, m, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || tiles <= 1) return e;
+    e = scan_inclusive(sums, sums, tiles, (double *)scratch + tiles, st);
+    if (e != hipSuccess) return e;
+    scan_add<<<(unsigned)tiles, SCAN_THREADS, 0, st>>>(out, m, sums);
+    return hipGetLastError();
+}
+
+// Inverse CDF: the smallest m with cdf[m] > u * cdf[M - 1] (clamped to M - 1).
+__global__ void __launch_bounds__(256) sample_search(const double *__restrict__ cdf, uint64_t M,
+                                                     const double *__restrict__ u, uint64_t shots,
+                                                     uint64_t *__restrict__ out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= shots) return;
+    const double target = u[i] * cdf[M - 1];
+    uint64_t lo = 0, hi = M;  // first index in [lo, hi) with cdf > target
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    out[i] = lo < M ? lo : M - 1;
+}
+
+hipError_t sample_outcomes(const double *cdf, uint64_t M, const double *u, uint64_t shots, uint64_t *out,
+                           hipStream_t st)
+{
+    if (shots == 0) return hipSuccess;
+    sample_search<<<grid_for(shots, 256, 0x7fffffffu), 256, 0, st>>>(cdf, M, u, shots, out);
+    return hipGetLastError();
+}
+
+// Projective collapse over the storage order: amplitudes whose physical
+// bits in `mask` differ from `val` become 0, the others are scaled.
+template <typename C>
+__global__ void __launch_bounds__(256) collapse_kernel(C *__restrict__ S, uint64_t N, uint64_t mask, uint64_t val,
+                                                       double scale)
+{
+    using T = decltype(C::x);
+    const T sc = (T)scale;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        const uint64_t p = sto<C>(i);  // storage position i holds physical index sto(i)
+        C a = S[i];
+        if ((p & mask) != val) {
+            a.x = 0;
+            a.y = 0;
+        } else {
+            a.x *= sc;
+            a.y *= sc;
+        }
+        S[i] = a;
+    }
+}
+
+hipError_t collapse(void *S, int n, int dtype, uint64_t mask, uint64_t val, double scale, hipStream_t st)
+{
+    const uint64_t N = 1ull << n;
+    const unsigned g = grid_for(N, 256, 16384);
+    if (dtype == 0) collapse_kernel<float2><<<g, 256, 0, st>>>((float2 *)S, N, mask, val, scale);
+    else collapse_kernel<double2><<<g, 256, 0, st>>>((double2 *)S, N, mask, val, scale);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- bandwidth probe

@@ -35,6 +35,16 @@ hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st);
 hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *dev_ops, bool mfma,
                    hipStream_t st);
 
+// Measurement. scan_inclusive: out[i] = in[0] + ... + in[i] in a fixed order
+// (in == out allowed); scratch: scan_scratch_bytes(m). sample_outcomes: for
+// each uniform u, the smallest m with cdf[m] > u * cdf[M - 1]. collapse: zero
+// the amplitudes whose physical bits in mask differ from val, scale the rest.
+size_t scan_scratch_bytes(uint64_t m);
+hipError_t scan_inclusive(const double *in, double *out, uint64_t m, void *scratch, hipStream_t st);
+hipError_t sample_outcomes(const double *cdf, uint64_t M, const double *u, uint64_t shots, uint64_t *out,
+                           hipStream_t st);
+hipError_t collapse(void *S, int n, int dtype, uint64_t mask, uint64_t val, double scale, hipStream_t st);
+
 // Plain HBM stream (bandwidth reference): mode 0 copy, 1 in place.
 hipError_t stream_probe(void *dst, const void *src, uint64_t bytes, int mode, hipStream_t st);
 

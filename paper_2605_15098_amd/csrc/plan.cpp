@@ -308,7 +308,11 @@ struct Builder {
             if (!G.wave.empty()) d.wave_off = build_table(G.wave, 6, nwave_bits);
             if (!G.glob.empty()) {
                 UGroup ug{(int)uterms.size(), (int)G.glob.size()};
-                for (auto &pr : G.glob) uterms.push_back(UTerm{pr.first, pr.second});
+                for (auto &pr : G.glob) {
+                    double c[2];
+                    cexp(pr.second, c);
+                    uterms.push_back(UTerm{pr.first, pr.second, c[0], c[1]});
+                }
                 d.uidx = (int)ugroups.size();
                 ugroups.push_back(ug);
             }
@@ -537,55 +541,113 @@ struct Builder {
             }
             pending.clear();
         };
-        // Dense windows (fuse_k 4 or 5): maximal runs of consecutive gates on
-        // local qubits whose union has at most fuse_k qubits; a run with two
-        // or more gates, at least one of them non-diagonal, becomes one
-        // MFMA op carrying the run's product.
-        std::vector<int> wend(q.size(), -1);
-        std::vector<uint32_t> wbits(q.size(), 0);
-        // the matrix-core op needs whole waves: 64 or more threads per block
-        if (cfg.fuse_k >= 4 && l >= 4 && l - logr >= 6) {
+        // Dense windows (fuse_k 4 or 5), formed over the pass's gate order:
+        // starting at a gate on local qubits, later gates join while the
+        // union of local qubits stays within fuse_k; a gate that cannot join
+        // but shares no qubit with the window is set aside and its qubits
+        // may no longer join (so it commutes with every window gate after
+        // it), which keeps diagonal runs whole. A window needs 4 or 5
+        // qubits of its own (no padding), a non-diagonal gate, and an
+        // estimated vector-ALU cost of its gates above the matrix-core
+        // cost of a 2^k x 2^k product (SV_FUSE_ALL=1 takes every such window:
+        // tests). `items` is the pass's gate order with windows as units.
+        struct Item {
+            bool window;
+            uint32_t bits;               // window local bits
+            std::vector<MGate> gates;    // the window's gates in order, or one gate
+        };
+        std::vector<Item> items;
+        bool any_window = false;
+        {
+            const bool fusing = cfg.fuse_k >= 4 && l >= 4 && l - logr >= 6;  // whole waves for the matrix op
+            const bool force = [] {
+                const char *e = std::getenv("SV_FUSE_ALL");
+                return e && e[0] == '1';
+            }();
+            const int kmax = std::min(cfg.fuse_k, l);
             auto local_bits = [&](const MGate &g) -> int64_t {
                 if (rank[g.t] < 0 || (g.c >= 0 && rank[g.c] < 0)) return -1;
                 uint32_t m = 1u << rank[g.t];
                 if (g.c >= 0) m |= 1u << rank[g.c];
                 return m;
             };
-            const int kmax = std::min(cfg.fuse_k, l);
-            size_t i = 0;
-            while (i < q.size()) {
-                const int64_t m0 = local_bits(q[i]);
+            auto mem_bits = [](const MGate &g) {
+                uint64_t m = 1ull << g.t;
+                if (g.c >= 0) m |= 1ull << g.c;
+                return m;
+            };
+            // vector-ALU work per amplitude of a gate in a block pass, in
+            // instructions (a 2x2 product: 8; controlled: half; Hadamard: 2;
+            // exchange: 1; a diagonal gate, folded into a run: 1), and of a
+            // matrix-core window: 4 * 2^k real multiply-adds per amplitude at
+            // twice (FP32) or once (FP64) the vector rate, plus its LDS round trip
+            auto valu = [&](const MGate &g) {
+                double c = g.cls == GC_DIAG ? 1.0 : (g.cls == GC_PERM ? 1.0 : (g.op == 0 ? 2.0 : 8.0));
+                return g.c >= 0 && g.cls != GC_DIAG ? 0.5 * c : c;
+            };
+            auto mfma_cost = [&](int k) { return (4 << k) / (cfg.dtype == 0 ? 2.0 : 1.0) + 8.0; };
+            std::vector<MGate> rest(q.begin(), q.end());
+            size_t pos = 0;
+            while (pos < rest.size()) {
+                const int64_t m0 = fusing ? local_bits(rest[pos]) : -1;
                 if (m0 < 0) {
-                    ++i;
+                    items.push_back(Item{false, 0, {rest[pos]}});
+                    ++pos;
                     continue;
                 }
-                uint32_t m = (uint32_t)m0;
-                bool dense = q[i].cls != GC_DIAG;
-                size_t e = i + 1;
-                for (; e < q.size(); ++e) {
-                    const int64_t mg = local_bits(q[e]);
-                    if (mg < 0 || __builtin_popcount(m | (uint32_t)mg) > kmax) break;
-                    m |= (uint32_t)mg;
-                    dense = dense || q[e].cls != GC_DIAG;
+                uint32_t W = (uint32_t)m0;
+                uint64_t Wmem = mem_bits(rest[pos]), blocked = 0;
+                std::vector<size_t> win{pos}, aside;
+                size_t j = pos + 1;
+                for (; j < rest.size(); ++j) {
+                    const MGate &h = rest[j];
+                    const int64_t mh = local_bits(h);
+                    const uint64_t hm = mem_bits(h);
+                    if (mh >= 0 && (hm & blocked) == 0 && __builtin_popcount(W | (uint32_t)mh) <= kmax) {
+                        W |= (uint32_t)mh;
+                        Wmem |= hm;
+                        win.push_back(j);
+                        continue;
+                    }
+                    if ((hm & Wmem) == 0 && aside.size() < 64) {
+                        aside.push_back(j);
+                        blocked |= hm;
+                        continue;
+                    }
+                    break;
                 }
-                if (e - i >= 2 && dense) {
-                    wend[i] = (int)e;
-                    wbits[i] = m;
+                bool dense = false;
+                double cost = 0.0;
+                for (size_t x : win) {
+                    dense = dense || rest[x].cls != GC_DIAG;
+                    cost += valu(rest[x]);
                 }
-                i = e;
+                const int K = __builtin_popcount(W);
+                if (win.size() < 2 || !dense || K < 4 || (!force && cost <= mfma_cost(K))) {
+                    items.push_back(Item{false, 0, {rest[pos]}});
+                    ++pos;
+                    continue;
+                }
+                Item it{true, W, {}};
+                for (size_t x : win) it.gates.push_back(rest[x]);
+                items.push_back(std::move(it));
+                any_window = true;
+                // continue with the set-aside gates, then the unscanned ones
+                std::vector<MGate> next;
+                for (size_t x : aside) next.push_back(rest[x]);
+                next.insert(next.end(), rest.begin() + (std::ptrdiff_t)j, rest.end());
+                rest.swap(next);
+                pos = 0;
             }
         }
         // matrix-core windows read the whole block from LDS
         half = allow_half && r >= 2 && (cfg.half_lds == 2 || (cfg.half_lds == 1 && ((size_t)ab << l) > kHalfFrom)) &&
-               std::find_if(wend.begin(), wend.end(), [](int e) { return e > 0; }) == wend.end();
-        auto emit_mfma = [&](size_t i0, size_t i1, uint32_t m) {
+               !any_window;
+        auto emit_mfma = [&](const std::vector<MGate> &wg, uint32_t m) {
             std::vector<int> wl;
             for (int b = 0; b < l; ++b)
                 if ((m >> b) & 1u) wl.push_back(b);
-            const int K = std::max(4, (int)wl.size());
-            for (int b = 0; b < l && (int)wl.size() < K; ++b)
-                if (!((m >> b) & 1u)) wl.push_back(b);
-            std::sort(wl.begin(), wl.end());
+            const int K = (int)wl.size();
             const int W = 1 << K;
             auto pos = [&](int memb) {
                 const int lb = rank[memb];
@@ -596,8 +658,7 @@ struct Builder {
             // U (row-major, interleaved re/im) = product of the gates, later gates on the left
             std::vector<double> U(2 * (size_t)W * W, 0.0);
             for (int x = 0; x < W; ++x) U[2 * ((size_t)x * W + x)] = 1.0;
-            for (size_t gi = i0; gi < i1; ++gi) {
-                const MGate &g = q[gi];
+            for (const MGate &g : wg) {
                 const int tp = pos(g.t), cp = g.c >= 0 ? pos(g.c) : -1;
                 for (int col = 0; col < W; ++col)
                     for (int x = 0; x < W; ++x) {
@@ -644,18 +705,17 @@ struct Builder {
             op.c = packed;
             op.m0 = mask;
             plan.ops.push_back(op);
-            plan.stats.fused += (int64_t)(i1 - i0);
+            plan.stats.fused += (int64_t)wg.size();
         };
         int hscale = 0;  // unnormalized Hadamards applied in this pass
         const int begin = (int)plan.ops.size();
-        for (size_t i = 0; i < q.size(); ++i) {
-            const MGate &g = q[i];
-            if (wend[i] > 0) {
+        for (size_t i = 0; i < items.size(); ++i) {
+            if (items[i].window) {
                 flush_diag();
-                emit_mfma(i, (size_t)wend[i], wbits[i]);
-                i = (size_t)wend[i] - 1;
+                emit_mfma(items[i].gates, items[i].bits);
                 continue;
             }
+            const MGate &g = items[i].gates[0];
             if (g.cls == GC_DIAG) {
                 pending.push_back(g);
                 continue;
@@ -668,9 +728,11 @@ struct Builder {
                 // data movement commutes with it), so the run sees this
                 // target as a register slot.
                 std::vector<int> nrb{lt};
-                for (size_t k = i + 1; k < q.size() && (int)nrb.size() < r; ++k) {
-                    if (q[k].cls == GC_DIAG) continue;
-                    const int x = rank[q[k].t];
+                for (size_t k = i + 1; k < items.size() && (int)nrb.size() < r; ++k) {
+                    if (items[k].window) continue;  // windows need no register slots
+                    const MGate &y = items[k].gates[0];
+                    if (y.cls == GC_DIAG) continue;
+                    const int x = rank[y.t];
                     if (std::find(nrb.begin(), nrb.end(), x) == nrb.end()) nrb.push_back(x);
                 }
                 for (int j = 0; j < r && (int)nrb.size() < r; ++j)

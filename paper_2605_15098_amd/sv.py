@@ -120,6 +120,9 @@ _SIGS = {
     "sv_qpe_readout": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                        ctypes.c_int32),
+    "sv_sample": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _VP, ctypes.c_size_t, _VP], ctypes.c_int32),
+    "sv_measure": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double,
+                    ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int32),
     "sv_qpe_readout_noalloc": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                                ctypes.c_int32),
@@ -315,6 +318,30 @@ def sv_qpe_readout(h, t: int):
     _check(load().sv_qpe_readout(_VP(h), int(t), ctypes.byref(m), ctypes.byref(phi),
                                  ctypes.byref(p)))
     return int(m.value), float(phi.value), float(p.value)
+
+
+def _qubit_array(qubits):
+    q = [] if qubits is None else [int(x) for x in qubits]
+    return (ctypes.c_int * max(1, len(q)))(*q), len(q)
+
+
+def sv_sample(h, qubits, uniforms) -> np.ndarray:
+    """Outcomes (uint64) of measuring `qubits` (None or []: all) for each uniform."""
+    qa, nq = _qubit_array(qubits)
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    out = np.empty(len(u), dtype=np.uint64)
+    _check(load().sv_sample(_VP(h), qa, nq, u.ctypes.data if len(u) else None, len(u),
+                            out.ctypes.data if len(u) else None))
+    return out
+
+
+def sv_measure(h, qubits, u: float):
+    """Projective measurement with uniform u: (outcome, probability); the state collapses."""
+    qa, nq = _qubit_array(qubits)
+    m = ctypes.c_uint64()
+    p = ctypes.c_double()
+    _check(load().sv_measure(_VP(h), qa, nq, float(u), ctypes.byref(m), ctypes.byref(p)))
+    return int(m.value), float(p.value)
 
 
 def sv_qpe_readout_noalloc(h, t: int):

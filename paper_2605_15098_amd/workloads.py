@@ -167,6 +167,23 @@ def random_circuit(n: int, depth: int, rng, kinds: Sequence[str] = RANDOM_KINDS)
     return gates_from_tuples(rows)
 
 
+def layered_dense_circuit(n: int, layers: int, rng) -> np.ndarray:
+    """Layers of dense rotations over neighbouring qubits (a layered ansatz):
+    each layer applies RX then RY with seeded angles on every qubit, then
+    CNOT(q, q+1) for even q and then for odd q. Gates on a few neighbouring
+    qubits come in long runs, the shape where a fused dense window replaces
+    many 2x2 products."""
+    rows: List[Tuple] = []
+    for _ in range(layers):
+        for q in range(n):
+            rows.append(("RX", q, -1, float(rng.random() * 2.0 * math.pi)))
+            rows.append(("RY", q, -1, float(rng.random() * 2.0 * math.pi)))
+        for start in (0, 1):
+            for q in range(start, n - 1, 2):
+                rows.append(("X", q + 1, q, 0.0))
+    return gates_from_tuples(rows)
+
+
 def random_u2(rng) -> np.ndarray:
     """A Haar-ish random 2x2 unitary as the 8-double (re, im) row-major record."""
     z = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))

@@ -3,7 +3,10 @@ formed in FP64 on the host, runs through the 16x16x4 matrix-core
 instructions (FP32 for complex64, FP64 for complex128) inside the block
 pass. Bars: complex64 <= 2e-5, complex128 <= 1e-12 against the FP64 oracle or
 the QPE closed form, exact QPE argmax; compiled and interpreted passes agree
-bit for bit (same handler, same instruction order).
+bit for bit (same handler, same instruction order). The matrix-core path is
+exercised with SV_FUSE_ALL=1 (every window of 4 or 5 qubits, whatever its
+cost); the default cost gate is checked on the QPE (no window qualifies:
+the same bits as fuse_k 1) and on layered dense circuits (windows qualify).
 """
 import sys
 
@@ -38,8 +41,9 @@ def run(n, dtype, g, sched, init=None):
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("fuse", [4, 5])
 @pytest.mark.parametrize("n,l", [(8, 6), (10, 10), (14, 10), (15, 12)])
-def test_fused_random_circuits_match_oracle(n, l, fuse, dtype):
+def test_fused_random_circuits_match_oracle(n, l, fuse, dtype, monkeypatch):
     """Blocks below 64 threads (l - 4 < 6) run unfused; the rest fuse."""
+    monkeypatch.setenv("SV_FUSE_ALL", "1")
     rng = np.random.default_rng(n + 10 * l + fuse)
     g = W.random_mixed_circuit(n, 150, rng)
     psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
@@ -51,7 +55,8 @@ def test_fused_random_circuits_match_oracle(n, l, fuse, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_fused_qpe_closed_form_and_argmax(dtype):
+def test_fused_qpe_closed_form_and_argmax(dtype, monkeypatch):
+    monkeypatch.setenv("SV_FUSE_ALL", "1")
     n, phi = 18, 0.6180339
     g = W.qpe_gates(n, phi)
     log(f"case fused qpe dtype={dtype}")
@@ -66,6 +71,7 @@ def test_fused_qpe_closed_form_and_argmax(dtype):
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_compiled_and_interpreted_fused_passes_agree_bitwise(dtype, monkeypatch):
+    monkeypatch.setenv("SV_FUSE_ALL", "1")
     rng = np.random.default_rng(5)
     n = 13
     g = W.random_mixed_circuit(n, 100, rng)
@@ -78,7 +84,8 @@ def test_compiled_and_interpreted_fused_passes_agree_bitwise(dtype, monkeypatch)
     assert np.array_equal(outs[0].view(np.uint8), outs[1].view(np.uint8))
 
 
-def test_fused_batch_matches_single():
+def test_fused_batch_matches_single(monkeypatch):
+    monkeypatch.setenv("SV_FUSE_ALL", "1")
     rng = np.random.default_rng(8)
     ns = [10, 12, 13]
     gl = [W.random_mixed_circuit(n, 80, rng) for n in ns]
@@ -90,3 +97,34 @@ def test_fused_batch_matches_single():
         want = oracle.apply(n, g)
         assert np.max(np.abs(s.state() - want)) <= TOL["c64"]
         s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_cost_gate_qpe_unfused_bits(dtype):
+    """On the QPE no window is worth the matrix cores (Hadamards and phase
+    runs are cheap on the vector ALUs): fuse_k 5 runs exactly the fuse_k 1
+    program, bit for bit, with grids that walk many blocks per work-group."""
+    n, phi = 22, W.phi_for_seed(22)
+    g = W.qpe_gates(n, phi)
+    outs = []
+    for k in (1, 5):
+        log(f"case cost-gate qpe dtype={dtype} k={k}")
+        got, st = run(n, dtype, g, sv.schedule(fuse_k=k))
+        assert st["fused"] == 0
+        outs.append(got)
+    assert np.array_equal(outs[0].view(np.uint8), outs[1].view(np.uint8))
+    assert np.max(np.abs(outs[0] - cf.qpe_state(n, phi))) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,k", [("c64", 5), ("c64", 4), ("c128", 4)])
+def test_cost_gated_windows_on_layered_dense_circuit(dtype, k):
+    """Layers of RX/RY on every qubit and CNOT ladders: windows qualify under
+    the default cost gate and the fused state matches the oracle."""
+    n = 18
+    rng = np.random.default_rng(18 + k)
+    g = W.layered_dense_circuit(n, 8, rng)
+    want = oracle.apply(n, g)
+    log(f"case cost-gated dense dtype={dtype} k={k}")
+    got, st = run(n, dtype, g, sv.schedule(block_qubits=12 if dtype == "c64" else 11, fuse_k=k))
+    assert st["fused"] > 0
+    assert np.max(np.abs(got - want)) <= TOL[dtype]

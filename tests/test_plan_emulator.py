@@ -141,12 +141,14 @@ def test_non_unit_diagonal_u2():
 @pytest.mark.parametrize("policy", [1, 2])
 @pytest.mark.parametrize("fuse", [4, 5])
 @pytest.mark.parametrize("n,l,dtype", [(6, 4, 1), (10, 6, 1), (12, 10, 1), (13, 13, 0), (14, 10, 0), (15, 11, 1)])
-def test_dense_fusion_programs(n, l, dtype, fuse, policy):
+def test_dense_fusion_programs(n, l, dtype, fuse, policy, monkeypatch):
     """Windows of up to `fuse` qubits as one matrix op (the emulator applies
     the operand-ordered table in FP64): complex128 tables hold the FP64
-    product, complex64 tables its FP32 rounding."""
+    product, complex64 tables its FP32 rounding. SV_FUSE_ALL takes every
+    window of 4 or 5 qubits, whatever its cost."""
     if fuse > l:
         pytest.skip("window larger than the block")
+    monkeypatch.setenv("SV_FUSE_ALL", "1")
     rng = np.random.default_rng(n * 10 + l + fuse)
     tol = 1e-12 if dtype == 1 else 1e-6
     g = W.random_mixed_circuit(n, 120, rng)
@@ -161,6 +163,33 @@ def test_dense_fusion_programs(n, l, dtype, fuse, policy):
                     sv.schedule(block_qubits=l, fuse_k=fuse, reg_qubits=4))
     # matrix-core windows need blocks of at least 64 threads (2^(l - 4))
     assert (st["fused"] > 0) == (l - 4 >= 6)
+
+
+def test_window_cost_gate():
+    """Without SV_FUSE_ALL a window is emitted only when its gates' estimated
+    vector-ALU work exceeds the matrix-core cost: the QPE's windows (a
+    Hadamard and phases per qubit) never qualify, so fuse_k 5 plans exactly
+    the fuse_k 1 program; layers of dense rotations over neighbouring qubits
+    do qualify, and every window has 4 or 5 qubits of its own."""
+    n, l = 20, 13
+    phi = W.phi_for_seed(7)
+    g = W.qpe_gates(n, phi)
+    for dt in ("c64", "c128"):
+        a = sv.sv_plan(n, dt, g, sv.schedule(block_qubits=l, fuse_k=5))
+        b = sv.sv_plan(n, dt, g, sv.schedule(block_qubits=l, fuse_k=1))
+        assert a["fused"] == 0 and a["passes"] == b["passes"]
+    dense = W.layered_dense_circuit(n, 6, np.random.default_rng(3))
+    # FP64 matrix cores run at half the FP32 rate: complex128 qualifies at k = 4
+    for dt, k in (("c64", 5), ("c64", 4), ("c128", 4)):
+        st = sv.sv_plan(n, dt, dense, sv.schedule(block_qubits=l, fuse_k=k))
+        assert st["fused"] > 0, (dt, k)
+    # the emulated programs of the gated windows match the oracle
+    psi0 = np.random.default_rng(4).normal(size=1 << 14) + 0j
+    psi0 /= np.linalg.norm(psi0)
+    dense14 = W.layered_dense_circuit(14, 6, np.random.default_rng(5))
+    for dtype, k, tol in ((1, 4, 1e-12), (0, 5, 1e-6)):
+        got, _ = run(14, dense14, psi0, dtype=dtype, l=12, fuse=k, policy=2)
+        assert np.max(np.abs(got - oracle.apply(14, dense14, psi0))) < tol
 
 
 @pytest.mark.parametrize("policy", [1, 2])
