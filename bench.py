@@ -246,6 +246,117 @@ def cpu_full():
     return out
 
 
+SWEEP_NS = (4, 8, 12, 16, 20, 22, 24, 26, 28, 30, 32, 34)
+
+
+def sweep_configs(n):
+    """The paper's experiment (Section IV-B) on this GPU: the unpartitioned
+    per-gate sweep (the paper's baseline), the paper's partitioning (LRU
+    victim, data-moving SWAP) over block sizes, the dependence-graph schedule
+    (the library default), and for n >= 28 the Infinity Cache outer tier."""
+    from paper_2605_15098_amd import sv
+
+    out = [("plain", "plain", sv.schedule("plain"))]
+    for l in sorted({min(n - 1, x) for x in (6, 8, 10, 12, 13, 14)}):
+        if l >= 2:
+            out.append((f"paper-lru-l{l}", "paper-lru", sv.paper_schedule(l)))
+    out.append(("graph-default", "graph", sv.schedule()))
+    if n >= 28:
+        for l2 in (22, 24, 26):
+            out.append((f"graph-outer-l2-{l2}", "graph-outer", sv.schedule(outer_qubits=l2)))
+    return out
+
+
+def sweep_gates(n):
+    import math
+    from paper_2605_15098_amd import workloads as W
+
+    # the paper's U(n): phi = 2^-t, read as counting value 1 with probability 1
+    return W.qpe_gates(n, math.ldexp(1.0, -(n - 1)))
+
+
+def sweep_precompile(cache_dir, workers=8):
+    """Compile every sweep configuration's passes into cache_dir (CPU only)."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    os.makedirs(cache_dir, exist_ok=True)
+    jobs = [(n, name) for n in SWEEP_NS for name, _, _ in sweep_configs(n)]
+    with ProcessPoolExecutor(workers) as pool:
+        list(pool.map(_precompile_one, [(cache_dir, n, name) for n, name in jobs]))
+    return len(jobs)
+
+
+def _precompile_one(args):
+    cache_dir, n, name = args
+    os.environ["SV_JIT_CACHE_DIR"] = cache_dir
+    from paper_2605_15098_amd import sv
+
+    sched = dict((nm, sc) for nm, _, sc in sweep_configs(n))[name]
+    if sched.mode == 1:
+        sv.sv_jit_precompile(n, "c64", sweep_gates(n), sched)
+
+
+def sweep(reps=2):
+    """Time every configuration of sweep_configs at every n (complex64, the
+    paper's precision): device ms of one circuit from |0...0> (median of
+    `reps` after one warm-up), passes, SWAPs, algorithmic GB/s, and the
+    readout check (counting value 1 with probability ~1); beside it the
+    oracle's float build on the host (whole circuit up to 24 qubits, a
+    strided sample of the circuit above) for the GPU/CPU speedup."""
+    import torch
+    from oracle import timing as T
+    from paper_2605_15098_amd import sv
+    from paper_2605_15098_amd import workloads as W
+
+    rows = []
+    for n in SWEEP_NS:
+        gates = sweep_gates(n)
+        G = W.qpe_gate_count(n)[0]
+        sim = sv.StateVector(n, "c64")
+        for name, family, sched in sweep_configs(n):
+            ms = []
+            for r in range(reps + 1):
+                sim.reset()
+                sim.apply(gates, sched)
+                st = sim.stats()
+                if r:
+                    ms.append(st["device_ms"])
+            m, _, pmax = sim.qpe_readout()
+            dms = float(np.median(ms))
+            row = {"n": n, "config": name, "family": family, "l": st["block_qubits"],
+                   "outer_qubits": int(sched.outer_qubits), "device_ms": dms, "passes": st["passes"],
+                   "swaps": st["swaps"], "phases": st["phases"], "gate_sweeps_per_s": G / (dms / 1e3),
+                   "effective_GBps": st["bytes"] / (dms / 1e3) / 1e9, "argmax": m, "p_max": pmax}
+            assert m == 1 and abs(pmax - 1.0) < 1e-4, (n, name, m, pmax)
+            rows.append(row)
+            log(f"sweep n={n} {name}: {dms:.3f} ms, {st['passes']} passes, {st['swaps']} swaps, "
+                f"{row['effective_GBps']:.0f} GB/s")
+        sim.close()
+        torch.cuda.empty_cache()
+    cpu = []
+    for n in SWEEP_NS:
+        if n > 32 or (8 << n) + (8 << 30) > T.mem_available():
+            continue
+        gates = sweep_gates(n)
+        body = gates[gates["op"] != 9]
+        S = T.alloc_state(n, "f32")
+        if n <= 24:
+            el = T.time_gate_loop(n, gates, S, "f32")
+            rate, what = len(body) / el, "whole circuit (SWAPs as data moves)"
+        else:
+            T.time_gate_loop(n, body[1:2], S, "f32")
+            probe = T.time_gate_loop(n, body[1:3], S, "f32") / 2
+            k = max(4, min(len(body), int(4.0 / max(probe, 1e-6))))
+            stride = max(1, len(body) // k)
+            sample = body[::stride][:k]
+            el = T.time_gate_loop(n, sample, S, "f32")
+            rate, what = len(sample) / el, f"every {stride}-th non-SWAP gate ({len(sample)} gates)"
+        del S
+        cpu.append({"n": n, "gate_sweeps_per_s": rate, "what": what})
+        log(f"sweep cpu n={n}: {rate:.2f} gate-sweeps/s ({what})")
+    return {"gpu": rows, "cpu_oracle_f32": cpu, "host": T.host_info()}
+
+
 def bench_batch(steps):
     """256 QPE instances (12..22 qubits, complex64) in one persistent launch
     under a captured graph, schedule picked by the batch autotuner."""
@@ -319,6 +430,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
                     help="only time the CPU oracle on whole circuits (median of 3) and print that record")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the paper's experiment: QPE with phi = 2^-t over n and block sizes")
+    ap.add_argument("--sweep-precompile", metavar="DIR",
+                    help="compile the sweep's passes into DIR on the host and exit (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 4 GiB read + 4 GiB write kernel "
                          "(the reference for HBM byte counters)")
@@ -329,6 +444,17 @@ def main():
         sys.exit(2)
     if args.cpu_full:
         print(json.dumps(cpu_full()), flush=True)
+        return
+    if args.sweep_precompile:
+        print(json.dumps({"precompiled": sweep_precompile(args.sweep_precompile)}), flush=True)
+        return
+    if args.sweep:
+        import torch
+        from paper_2605_15098_amd import sv
+
+        sv.load()
+        torch.cuda.set_device(0)
+        print(json.dumps(sweep()), flush=True)
         return
 
     import torch

@@ -15,7 +15,10 @@
 #include <cstdlib>
 #include <vector>
 
+#ifndef SV_EMU_NO_JIT
 #include "../../paper_2605_15098_amd/csrc/jit.h"
+#endif
+#include "../../paper_2605_15098_amd/csrc/plan.h"
 #include "../../paper_2605_15098_amd/csrc/plan.h"
 
 using cd = std::complex<double>;
@@ -419,6 +422,7 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
 // Plan the circuit and compile every generated block-pass kernel (no GPU
 // needed). Returns the number of kernels compiled, or -1 with the first
 // compiler log copied to log_out.
+#ifndef SV_EMU_NO_JIT  // the sanitizer build leaves the run-time compiler out
 extern "C" int emu_jit_check(int n, int dtype, int l, int logr, int policy, int remap, int diag_free, int fuse_k,
                              const void *gates, size_t m, char *log_out, size_t log_cap)
 {
@@ -447,3 +451,4 @@ extern "C" int emu_jit_check(int n, int dtype, int l, int logr, int policy, int 
     }
     return count;
 }
+#endif

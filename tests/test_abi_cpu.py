@@ -292,3 +292,28 @@ def test_oracle_float_build_tracks_the_fp64_oracle():
     S64 = T.alloc_state(n, "f64")
     T.time_gate_loop(n, g, S64, "f64")
     assert np.array_equal(S64[0::2] + 1j * S64[1::2], want)
+
+
+@pytest.mark.slow
+def test_host_code_under_address_and_undefined_sanitizers(tmp_path):
+    """The planner, the emulator of its device programs and the C oracle,
+    built with -fsanitize=address,undefined, plan and emulate circuits under
+    every schedule option and run the oracle: no sanitizer report."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    csrc = os.path.join(root, "paper_2605_15098_amd", "csrc")
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g", "-O1"]
+    obj = str(tmp_path / "oracle.o")
+    subprocess.run(["gcc", "-std=c11", "-c", os.path.join(root, "oracle", "sv_oracle.c"), "-o", obj] + san,
+                   check=True)
+    exe = str(tmp_path / "sanitized")
+    # host code only: no HIP runtime (the run-time compiler's entry is left out)
+    subprocess.run(["g++", "-std=c++17", "-DSV_EMU_NO_JIT",
+                    os.path.join(here, "emu", "sanitize_driver.cpp"), os.path.join(here, "emu", "k2_emulator.cpp"),
+                    os.path.join(csrc, "plan.cpp"), obj, "-o", exe, "-lm"] + san, check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-4000:])
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert "sanitized run" in r.stdout
