@@ -58,6 +58,8 @@ def _lib(mutant: int = 0):
         lib.or_argmax.argtypes = [ctypes.c_int64, dp]
         lib.or_argmax.restype = ctypes.c_int64
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_apply_kq.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ctypes.c_int, ip, dp]
+        lib.or_apply_kq.restype = ctypes.c_int
         _libs[mutant] = lib
         return lib
 
@@ -159,3 +161,32 @@ def qpe_readout(n: int, state: np.ndarray):
 
 def num_threads() -> int:
     return int(_lib().or_num_threads())
+
+
+def apply_kq(n: int, state, targets, controls, U) -> np.ndarray:
+    """A k-qubit unitary U (2^k x 2^k, row = output, bit b of the row index =
+    qubit targets[b]) on `targets`, where every qubit of `controls` is 1."""
+    s = np.array(state, dtype=np.complex128, copy=True)
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    c = np.ascontiguousarray(controls if len(controls) else [0], dtype=np.int32)
+    u = np.ascontiguousarray(np.asarray(U, dtype=np.complex128).reshape(-1).view(np.float64))
+    if u.size != 2 * (1 << (2 * len(t))):
+        raise ValueError("U must be 2^k x 2^k")
+    if _lib().or_apply_kq(n, _dp(s.view(np.float64)), len(t), _ip(t), len(controls), _ip(c), _dp(u)):
+        raise ValueError("malformed gate")
+    return s
+
+
+def apply_ex(n: int, gates, state=None) -> np.ndarray:
+    """Apply extended gates in order: each is (kind, targets, controls, U or
+    None): kind "U" with a 2^k x 2^k U, or a gate name of the standard set
+    (with "theta" in U's place for rotations) for one target."""
+    s = zero_state(n) if state is None else np.array(state, dtype=np.complex128, copy=True)
+    for kind, targets, controls, arg in gates:
+        if kind == "U":
+            U = arg
+        else:
+            U = gate_matrix({"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "P": 7}[kind],
+                            0.0 if arg is None else float(arg))
+        s = apply_kq(n, s, targets, controls, U)
+    return s

@@ -183,6 +183,57 @@ void or_zero_state(int n, or_real *S)
 }
 
 #ifndef OR_FLOAT
+/* ---- General gates (a wider front end than the paper's single control) ----
+ *
+ * A k-qubit unitary U (2^k x 2^k, row-major (re, im) pairs, row = output)
+ * on targets t[0..k-1], applied where every control bit c[0..nc-1] is 1:
+ * for each index j whose target bits are 0 and whose control bits are 1,
+ * the 2^k amplitudes a_x = S[j + sum_b x_b 2^t[b]] (x over 0 .. 2^k - 1, bit
+ * b of x = qubit t[b]) become sum_y U[x][y] a_y. This is Algorithm 1's pair
+ * update widened from 2 amplitudes to 2^k, with the control predicate over
+ * several bits. Returns 0, or -1 for a malformed gate. */
+int or_apply_kq(int n, or_real *S, int k, const int *t, int nc, const int *c, const double *U)
+{
+    if (n < 1 || n > 40 || k < 1 || k > 6 || nc < 0 || nc > 16 || k + nc > n) return -1;
+    uint64_t tmask = 0, cmask = 0;
+    for (int b = 0; b < k; ++b) {
+        if (t[b] < 0 || t[b] >= n || ((tmask >> t[b]) & 1ull)) return -1;
+        tmask |= 1ull << t[b];
+    }
+    for (int b = 0; b < nc; ++b) {
+        if (c[b] < 0 || c[b] >= n || (((tmask | cmask) >> c[b]) & 1ull)) return -1;
+        cmask |= 1ull << c[b];
+    }
+    const int K = 1 << k;
+    const uint64_t N = 1ull << n;
+#pragma omp parallel for schedule(static) if (n >= 14)
+    for (int64_t ji = 0; ji < (int64_t)N; ++ji) {
+        const uint64_t j = (uint64_t)ji;
+        if ((j & tmask) != 0 || (j & cmask) != cmask) continue;
+        double ar[64], ai[64];
+        uint64_t idx[64];
+        for (int x = 0; x < K; ++x) {
+            uint64_t off = 0;
+            for (int b = 0; b < k; ++b)
+                if ((x >> b) & 1) off |= 1ull << t[b];
+            idx[x] = j | off;
+            ar[x] = S[2 * idx[x]];
+            ai[x] = S[2 * idx[x] + 1];
+        }
+        for (int x = 0; x < K; ++x) {
+            double re = 0.0, im = 0.0;
+            for (int y = 0; y < K; ++y) {
+                const double ur = U[2 * (x * K + y)], ui = U[2 * (x * K + y) + 1];
+                re += ur * ar[y] - ui * ai[y];
+                im += ur * ai[y] + ui * ar[y];
+            }
+            S[2 * idx[x]] = (or_real)re;
+            S[2 * idx[x] + 1] = (or_real)im;
+        }
+    }
+    return 0;
+}
+
 /* |S_i|^2 in binary64. */
 void or_probabilities(int n, const double *S, double *P)
 {
