@@ -221,6 +221,54 @@ sv_status sv_set_stream(sv_handle h, void *hip_stream);
  * (fuse_k > 6), DEVICE. No gate is applied when validation fails. */
 sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv_schedule *s);
 
+/* ---- general front end (wider than the paper's gate set: Section III-A
+ * defines one control per gate) ----
+ * An extended gate: any gate kind of sv_gate on one target with any number
+ * of controls, a controlled SWAP, or SV_UK, a dense 2^k x 2^k unitary on k
+ * targets (k = 1..6), with up to 16 controls (the gate acts where every
+ * control qubit is 1). For SV_UK, uk points to 2 * 4^k doubles: row-major
+ * (re, im), row = output, and bit b of a row or column index is the value of
+ * qubit targets[b]; it is borrowed for the call. */
+#define SV_UK 10
+#define SV_MAX_TARGETS 6
+#define SV_MAX_CONTROLS 16
+typedef struct {
+    int32_t op;         /* SV_H .. SV_SWAP or SV_UK                            */
+    int32_t ntargets;   /* 1; 2 for SV_SWAP; k for SV_UK                       */
+    int32_t ncontrols;  /* 0 .. SV_MAX_CONTROLS                                */
+    int32_t pad;
+    int32_t targets[SV_MAX_TARGETS];
+    int32_t controls[SV_MAX_CONTROLS];
+    double theta;       /* radians, for RX/RY/RZ/P                             */
+    double u[8];        /* SV_U2: row-major 2x2 (re, im)                       */
+    const double *uk;   /* SV_UK: the 2^k x 2^k matrix                         */
+} sv_gate_ex;
+
+/* Apply m extended gates in order (calls accumulate, like sv_apply_circuit).
+ * Runs of gates that sv_gate can express (one target, at most one control,
+ * uncontrolled SWAP) go through the schedule s as sv_apply_circuit would
+ * apply them; every other gate is one sweep over the state (a group of 2^k
+ * amplitudes per thread) on the current layout. All gates are validated
+ * before any is applied. Errors: INVALID_ARG (qubits out of range or
+ * repeated, counts out of range, non-finite numbers, null uk), UNSUPPORTED
+ * (k > 6, more than 16 controls, a tuner in s), DEVICE. */
+sv_status sv_apply_circuit_ex(sv_handle h, const sv_gate_ex *gates, size_t m, const sv_schedule *s);
+
+/* Read an OpenQASM 2.0 program (host only; no handle, no device). Writes the
+ * first min(cap, *count) records to gates (gates may be null when cap is 0)
+ * and sets *count to the program's number of records and *nqubits to the
+ * total size of its quantum registers (numbered in declaration order). The
+ * standard library (include "qelib1.inc") is built in; user gates are
+ * expanded; measure and barrier are dropped; reset, if and opaque gates give
+ * UNSUPPORTED, as do the relative-phase gates rccx and rc3x. Gate matrices:
+ * U(theta, phi, lambda) = [[c, -e^{i lambda} s], [e^{i phi} s, e^{i(phi +
+ * lambda)} c]] with c = cos(theta/2), s = sin(theta/2); rx/ry/rz =
+ * exp(-i theta sigma/2); p = u1 = diag(1, e^{i lambda}); rzz/rxx =
+ * exp(-i theta P(x)P/2). Records never carry SV_UK. Errors: INVALID_ARG
+ * (syntax, unknown names, sizes; the message names the line), UNSUPPORTED,
+ * OUT_OF_MEMORY. */
+sv_status sv_qasm_parse(const char *text, sv_gate_ex *gates, size_t cap, size_t *count, int *nqubits);
+
 /* Compile ahead of time the block-pass kernels that `repeats` consecutive
  * sv_apply_circuit calls of this circuit and schedule will use from the
  * current layout (a circuit whose SWAP gates relabel qubits changes the

@@ -19,6 +19,7 @@
 #include "launch.h"
 #include "mlp.h"
 #include "plan.h"
+#include "qasm.h"
 
 namespace {
 
@@ -236,7 +237,7 @@ sv_status check_schedule(const sv_schedule *s, int dtype)
     return SV_OK;
 }
 
-sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
+sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits, bool record = true)
 {
     const auto tu0 = std::chrono::steady_clock::now();
     if (!plan.ops.empty()) {
@@ -343,7 +344,7 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
         }
         return SV_OK;
     };
-    SV_HIP(hipEventRecord(h->ev0, h->stream), "hipEventRecord");
+    if (record) SV_HIP(hipEventRecord(h->ev0, h->stream), "hipEventRecord");
     for (size_t si = 0; si < plan.steps.size();) {
         const svp::Step &s = plan.steps[si];
         if (s.kind == svp::ST_K1) {
@@ -401,8 +402,10 @@ sv_status run_plan(sv_handle h, const svp::Plan &plan, int outer_qubits)
         }
         si = sj;
     }
-    SV_HIP(hipEventRecord(h->ev1, h->stream), "hipEventRecord");
-    h->timed = true;
+    if (record) {
+        SV_HIP(hipEventRecord(h->ev1, h->stream), "hipEventRecord");
+        h->timed = true;
+    }
     if (trace) {
         const auto tp2 = std::chrono::steady_clock::now();
         std::fprintf(stderr, "[sv] prepare %.3f ms, launch %.3f ms, %zu steps\n",
@@ -594,6 +597,173 @@ sv_status sv_apply_circuit(sv_handle h, const sv_gate *gates, size_t m, const sv
     std::memset(&h->st, 0, sizeof(h->st));
     fill_stats(&h->st, c, plan);
     h->st.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return SV_OK;
+}
+
+static bool finite_all(const double *x, size_t k)
+{
+    for (size_t i = 0; i < k; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+// An extended gate that sv_gate can express, as that record (else false).
+static bool as_plain_gate(const sv_gate_ex &g, svp::RawGate &r)
+{
+    if (g.op == SV_UK) return false;
+    if (g.op == SV_SWAP) {
+        if (g.ncontrols != 0) return false;
+        r = svp::RawGate{SV_SWAP, g.targets[0], -1, g.targets[1], 0.0, {0}};
+        return true;
+    }
+    if (g.ncontrols > 1) return false;
+    r = svp::RawGate{g.op, g.targets[0], g.ncontrols ? g.controls[0] : -1, -1, g.theta, {0}};
+    std::memcpy(r.u, g.u, sizeof r.u);
+    return true;
+}
+
+static sv_status check_gate_ex(const sv_gate_ex &g, int n, size_t i)
+{
+    const std::string at = " (gate " + std::to_string(i) + ")";
+    if (g.op < SV_H || g.op > SV_UK) return fail(SV_ERR_INVALID_ARG, "unknown op" + at);
+    const int want = g.op == SV_SWAP ? 2 : (g.op == SV_UK ? g.ntargets : 1);
+    if (g.op == SV_UK && g.ntargets > SV_MAX_TARGETS) return fail(SV_ERR_UNSUPPORTED, "more than 6 targets" + at);
+    if (g.ntargets != want || want < 1) return fail(SV_ERR_INVALID_ARG, "wrong number of targets" + at);
+    if (g.ncontrols > SV_MAX_CONTROLS) return fail(SV_ERR_UNSUPPORTED, "more than 16 controls" + at);
+    if (g.ncontrols < 0) return fail(SV_ERR_INVALID_ARG, "negative control count" + at);
+    uint64_t seen = 0;
+    for (int b = 0; b < g.ntargets + g.ncontrols; ++b) {
+        const int q = b < g.ntargets ? g.targets[b] : g.controls[b - g.ntargets];
+        if (q < 0 || q >= n || ((seen >> q) & 1ull)) return fail(SV_ERR_INVALID_ARG, "qubit out of range or repeated" + at);
+        seen |= 1ull << q;
+    }
+    if (!std::isfinite(g.theta)) return fail(SV_ERR_INVALID_ARG, "non-finite angle" + at);
+    if (g.op == SV_U2 && !finite_all(g.u, 8)) return fail(SV_ERR_INVALID_ARG, "non-finite matrix entry" + at);
+    if (g.op == SV_UK) {
+        if (!g.uk) return fail(SV_ERR_INVALID_ARG, "null unitary" + at);
+        if (!finite_all(g.uk, (size_t)2 << (2 * g.ntargets))) return fail(SV_ERR_INVALID_ARG, "non-finite matrix entry" + at);
+    }
+    return SV_OK;
+}
+
+sv_status sv_apply_circuit_ex(sv_handle h, const sv_gate_ex *gates, size_t m, const sv_schedule *s)
+{
+    if (sv_status st = check_handle(h)) return st;
+    if (sv_status st = check_schedule(s, h->dtype)) return st;
+    if (s && s->tuner != SV_TUNER_NONE) return fail(SV_ERR_UNSUPPORTED, "the tuner takes sv_gate circuits");
+    if (m > 0 && !gates) return fail(SV_ERR_INVALID_ARG, "gate array is null");
+    for (size_t i = 0; i < m; ++i)
+        if (sv_status st = check_gate_ex(gates[i], h->n, i)) return st;
+    svp::PlanConfig c = config_from(h, s);
+    sv_stats tot{};
+    double plan_ms = 0.0;
+    std::vector<svp::RawGate> seg;
+    auto flush = [&]() -> sv_status {
+        if (seg.empty()) return SV_OK;
+        const auto p0 = std::chrono::steady_clock::now();
+        svp::Plan plan;
+        std::string err = svp::make_plan(c, seg.data(), seg.size(), h->l2p, plan);
+        if (!err.empty()) return fail(SV_ERR_INVALID_ARG, err);
+        plan_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - p0).count();
+        if (sv_status st = run_plan(h, plan, s ? s->outer_qubits : 0, false)) return st;
+        h->l2p = plan.l2p_after;
+        sv_stats one{};
+        fill_stats(&one, c, plan);
+        tot.gates += one.gates;
+        tot.swaps += one.swaps;
+        tot.phases += one.phases;
+        tot.passes += one.passes;
+        tot.fused += one.fused;
+        tot.bytes += one.bytes;
+        tot.block_qubits = one.block_qubits;
+        seg.clear();
+        return SV_OK;
+    };
+    // the matrices of the extended gates, formed in binary64 and rounded
+    // once to the state's precision, uploaded together before any gate runs
+    const size_t ab = amp_bytes(h->dtype);
+    std::vector<size_t> moff(m, 0);
+    std::vector<unsigned char> mats;
+    for (size_t i = 0; i < m; ++i) {
+        const sv_gate_ex &g = gates[i];
+        svp::RawGate r;
+        if (as_plain_gate(g, r)) continue;
+        const int k = g.op == SV_UK ? g.ntargets : (g.op == SV_SWAP ? 2 : 1);
+        const int D = 1 << k;
+        std::vector<double> U(2 * (size_t)D * D, 0.0);
+        if (g.op == SV_UK) {
+            std::memcpy(U.data(), g.uk, U.size() * sizeof(double));
+        } else if (g.op == SV_SWAP) {
+            for (int x = 0; x < 4; ++x) U[2 * (x * 4 + ((x & 1) << 1 | (x >> 1)))] = 1.0;
+        } else {
+            int cls = 0;
+            svp::gate_matrix(g.op, g.theta, g.u, U.data(), &cls);
+        }
+        moff[i] = mats.size();
+        mats.resize(mats.size() + (((size_t)D * D * ab + 255) & ~(size_t)255));
+        unsigned char *dst = mats.data() + moff[i];
+        if (h->dtype == SV_COMPLEX64) {
+            for (size_t e = 0; e < U.size(); ++e) {
+                const float f = (float)U[e];
+                std::memcpy(dst + e * sizeof(float), &f, sizeof f);
+            }
+        } else {
+            std::memcpy(dst, U.data(), U.size() * sizeof(double));
+        }
+    }
+    if (!mats.empty()) {
+        if (sv_status st = ensure_scratch(h, mats.size())) return st;
+        SV_HIP(hipMemcpyAsync(h->scratch, mats.data(), mats.size(), hipMemcpyHostToDevice, h->stream), "upload");
+        SV_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    }
+    SV_HIP(hipEventRecord(h->ev0, h->stream), "hipEventRecord");
+    for (size_t i = 0; i < m; ++i) {
+        const sv_gate_ex &g = gates[i];
+        svp::RawGate r;
+        if (as_plain_gate(g, r)) {
+            seg.push_back(r);
+            continue;
+        }
+        if (sv_status st = flush()) return st;
+        const int k = g.op == SV_UK ? g.ntargets : (g.op == SV_SWAP ? 2 : 1);
+        int tb[SV_MAX_TARGETS], cb[SV_MAX_CONTROLS];
+        for (int b = 0; b < k; ++b) tb[b] = h->l2p[g.targets[b]];
+        for (int b = 0; b < g.ncontrols; ++b) cb[b] = h->l2p[g.controls[b]];
+        if (launch_fault()) return fail(SV_ERR_DEVICE, "injected launch failure");
+        SV_HIP(svk::kq_gate(h->buf, h->n, h->dtype, tb, k, cb, g.ncontrols, (char *)h->scratch + moff[i], h->stream),
+               "kernel launch");
+        tot.gates += 1;
+        tot.passes += 1;
+        tot.bytes += std::ldexp(2.0 * (double)ab, h->n - g.ncontrols);
+    }
+    if (sv_status st = flush()) return st;
+    SV_HIP(hipEventRecord(h->ev1, h->stream), "hipEventRecord");
+    h->timed = true;
+    std::memset(&h->st, 0, sizeof(h->st));
+    fill_stats(&h->st, c, svp::Plan());
+    h->st.gates = tot.gates;
+    h->st.swaps = tot.swaps;
+    h->st.phases = tot.phases;
+    h->st.passes = tot.passes;
+    h->st.fused = tot.fused;
+    h->st.bytes = tot.bytes;
+    h->st.block_qubits = tot.block_qubits;
+    h->st.plan_ms = plan_ms;
+    return SV_OK;
+}
+
+sv_status sv_qasm_parse(const char *text, sv_gate_ex *gates, size_t cap, size_t *count, int *nqubits)
+{
+    if (!text || !count || !nqubits) return fail(SV_ERR_INVALID_ARG, "null text, count or nqubits");
+    if (cap > 0 && !gates) return fail(SV_ERR_INVALID_ARG, "null gate array with nonzero capacity");
+    std::vector<sv_gate_ex> out;
+    int nq = 0;
+    std::string err;
+    const sv_status st = svq::parse(text, out, nq, err);
+    if (st != SV_OK) return fail(st, err);
+    *count = out.size();
+    *nqubits = nq;
+    if (cap > 0) std::memcpy(gates, out.data(), std::min(cap, out.size()) * sizeof(sv_gate_ex));
     return SV_OK;
 }
 

@@ -20,6 +20,7 @@
 // bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 
@@ -183,6 +184,85 @@ template <typename T> static hipError_t k1_launch(void *Sv, int n, const svp::MG
 hipError_t k1_gate(void *S, int n, int dtype, const svp::MGate &g, hipStream_t st)
 {
     return dtype == 0 ? k1_launch<float>(S, n, g, st) : k1_launch<double>(S, n, g, st);
+}
+
+// ---------------------------------------------------------------- extended gates
+
+// A k-qubit unitary (2^k x 2^k, row-major, the state's precision; bit b of
+// the row index = target b) on physical target bits where every physical
+// bit of cmask is 1: one thread per group of 2^k amplitudes. The group base
+// inserts zeros at the fixed bits (targets and controls, ascending) into
+// the thread number and sets the controls; the matrix is read at uniform
+// addresses (scalar loads), the 2^k outputs are stored after all inputs are
+// in registers.
+template <typename C, int K>
+__global__ void __launch_bounds__(128) kq_kernel(C *__restrict__ S, uint64_t ngroups, KqArg a, const C *__restrict__ U)
+{
+    constexpr int D = 1 << K;
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    uint64_t j = g;
+    for (int i = 0; i < a.nfixed; ++i) j = insert0(j, a.fixed[i]);
+    j |= a.cmask;
+    const uint64_t sj = sto<C>(j);
+    // storage offset of group member x (the order is linear, so offsets XOR)
+    auto at = [&](int x) {
+        uint64_t off = sj;
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if ((x >> b) & 1) off ^= a.toff[b];
+        return off;
+    };
+    C v[D];
+#pragma unroll
+    for (int x = 0; x < D; ++x) v[x] = S[at(x)];
+#pragma unroll
+    for (int x = 0; x < D; ++x) {
+        C acc = mk<C>(0.0, 0.0);
+#pragma unroll
+        for (int y = 0; y < D; ++y) {
+            const C u = U[x * D + y];
+            acc.x = xfma(u.x, v[y].x, xfma(-u.y, v[y].y, acc.x));
+            acc.y = xfma(u.x, v[y].y, xfma(u.y, v[y].x, acc.y));
+        }
+        S[at(x)] = acc;
+    }
+}
+
+template <typename C> static hipError_t kq_launch(void *S, int n, const KqArg &a, const void *U, hipStream_t st)
+{
+    const uint64_t ngroups = 1ull << (n - a.nfixed);
+    const unsigned grid = (unsigned)((ngroups + 127) / 128);
+    switch (a.k) {
+    case 1: kq_kernel<C, 1><<<grid, 128, 0, st>>>((C *)S, ngroups, a, (const C *)U); break;
+    case 2: kq_kernel<C, 2><<<grid, 128, 0, st>>>((C *)S, ngroups, a, (const C *)U); break;
+    case 3: kq_kernel<C, 3><<<grid, 128, 0, st>>>((C *)S, ngroups, a, (const C *)U); break;
+    case 4: kq_kernel<C, 4><<<grid, 128, 0, st>>>((C *)S, ngroups, a, (const C *)U); break;
+    case 5: kq_kernel<C, 5><<<grid, 128, 0, st>>>((C *)S, ngroups, a, (const C *)U); break;
+    case 6: kq_kernel<C, 6><<<grid, 128, 0, st>>>((C *)S, ngroups, a, (const C *)U); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t kq_gate(void *S, int n, int dtype, const int *tbits, int k, const int *cbits, int nc, const void *U,
+                   hipStream_t st)
+{
+    if (k < 1 || k > 6 || nc < 0 || k + nc > n || k + nc > 24) return hipErrorInvalidValue;
+    KqArg a{};
+    a.k = k;
+    int fixed[24];
+    for (int b = 0; b < k; ++b) fixed[b] = tbits[b];
+    for (int b = 0; b < nc; ++b) {
+        fixed[k + b] = cbits[b];
+        a.cmask |= 1ull << cbits[b];
+    }
+    a.nfixed = k + nc;
+    std::sort(fixed, fixed + a.nfixed);
+    for (int i = 0; i < a.nfixed; ++i) a.fixed[i] = (int8_t)fixed[i];
+    for (int b = 0; b < k; ++b)
+        a.toff[b] = dtype == 0 ? sto<float2>(1ull << tbits[b]) : sto<double2>(1ull << tbits[b]);
+    return dtype == 0 ? kq_launch<float2>(S, n, a, U, st) : kq_launch<double2>(S, n, a, U, st);
 }
 
 // ---------------------------------------------------------------- k3

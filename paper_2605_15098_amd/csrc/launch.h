@@ -31,6 +31,17 @@ hipError_t k6_batch(int dtype, int logr, unsigned grid, unsigned threads, size_t
 hipError_t zero_u32(unsigned *p, uint32_t n, hipStream_t st);
 hipError_t k1_gate(void *S, int n, int dtype, const svp::MGate &g, hipStream_t st);
 hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st);
+// Extended gate: a k-qubit unitary U (device, 4^k amplitudes of the state's
+// type, row-major, bit b of the row index = target b) on physical target bits
+// tbits[0..k-1] where every physical bit cbits[0..nc-1] is 1 (k <= 6).
+struct KqArg {
+    int8_t fixed[24];   // targets and controls, ascending
+    int32_t nfixed, k;
+    uint64_t cmask;
+    uint64_t toff[6];   // storage-order offset of each target bit
+};
+hipError_t kq_gate(void *S, int n, int dtype, const int *tbits, int k, const int *cbits, int nc, const void *U,
+                   hipStream_t st);
 // mfma: the op list holds matrix-core windows.
 hipError_t k2_pass(void *S, int n, int dtype, int logr, const K2Args &a, const svp::K2Op *dev_ops, bool mfma,
                    hipStream_t st);

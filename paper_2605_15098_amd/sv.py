@@ -94,6 +94,19 @@ def paper_schedule(block_qubits: int) -> sv_schedule:
     return schedule("partitioned", block_qubits, swap_policy="lru", remap="explicit", diag_free=False)
 
 
+SV_UK = 10
+SV_MAX_TARGETS, SV_MAX_CONTROLS = 6, 16
+GATE_OPS = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "P": 7, "U2": 8, "SWAP": 9, "U": SV_UK}
+OP_NAMES = {v: k for k, v in GATE_OPS.items()}
+
+
+class sv_gate_ex(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("ntargets", ctypes.c_int32), ("ncontrols", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("targets", ctypes.c_int32 * SV_MAX_TARGETS),
+                ("controls", ctypes.c_int32 * SV_MAX_CONTROLS), ("theta", ctypes.c_double),
+                ("u", ctypes.c_double * 8), ("uk", ctypes.c_void_p)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -151,6 +164,10 @@ _SIGS = {
     "sv_set_kernel_timing": ([_VP, ctypes.c_int], ctypes.c_int32),
     "sv_debug_inject_fault": ([ctypes.c_int], ctypes.c_int32),
     "sv_stream_probe": ([_VP, _VP, ctypes.c_size_t, ctypes.c_int, _VP], ctypes.c_int32),
+    "sv_apply_circuit_ex": ([_VP, ctypes.POINTER(sv_gate_ex), ctypes.c_size_t, ctypes.POINTER(sv_schedule)],
+                            ctypes.c_int32),
+    "sv_qasm_parse": ([ctypes.c_char_p, ctypes.POINTER(sv_gate_ex), ctypes.c_size_t,
+                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)], ctypes.c_int32),
 }
 
 
@@ -501,6 +518,77 @@ def sv_debug_inject_fault(kind: int) -> None:
     _check(load().sv_debug_inject_fault(int(kind)))
 
 
+# ---------------------------------------------------------------- general front end
+
+def ex_gates(gates):
+    """sv_gate_ex records for a list of (kind, targets, controls, arg):
+    kind a GATE_OPS name ("U" for a 2^k x 2^k matrix, "U2" for a 2x2 one,
+    a rotation or "P" with the angle as arg). Returns (array, keep-alive list
+    of the matrices the records point to)."""
+    arr = (sv_gate_ex * max(1, len(gates)))()
+    keep = []
+    for i, (kind, targets, controls, arg) in enumerate(gates):
+        r = arr[i]
+        r.op = GATE_OPS[kind]
+        targets, controls = list(targets), list(controls)
+        r.ntargets, r.ncontrols = len(targets), len(controls)
+        if len(targets) > SV_MAX_TARGETS or len(controls) > SV_MAX_CONTROLS:
+            raise ValueError("too many targets or controls")
+        for b, q in enumerate(targets):
+            r.targets[b] = int(q)
+        for b, q in enumerate(controls):
+            r.controls[b] = int(q)
+        if kind in ("RX", "RY", "RZ", "P"):
+            r.theta = float(arg)
+        elif kind == "U2":
+            m = np.asarray(arg, dtype=np.complex128).reshape(2, 2)
+            for e in range(4):
+                r.u[2 * e], r.u[2 * e + 1] = m.flat[e].real, m.flat[e].imag
+        elif kind == "U":
+            m = np.ascontiguousarray(np.asarray(arg, dtype=np.complex128))
+            if m.shape != (1 << len(targets), 1 << len(targets)):
+                raise ValueError("the matrix of a k-target gate is 2^k x 2^k")
+            keep.append(m)
+            r.uk = m.ctypes.data
+    return arr, keep
+
+
+def ex_tuples(arr, count):
+    """The inverse of ex_gates for records without matrices (parser output)."""
+    out = []
+    for i in range(count):
+        r = arr[i]
+        kind = OP_NAMES[r.op]
+        t = [int(r.targets[b]) for b in range(r.ntargets)]
+        c = [int(r.controls[b]) for b in range(r.ncontrols)]
+        if kind in ("RX", "RY", "RZ", "P"):
+            arg = float(r.theta)
+        elif kind == "U2":
+            arg = np.array([complex(r.u[2 * e], r.u[2 * e + 1]) for e in range(4)]).reshape(2, 2)
+        else:
+            arg = None
+        out.append((kind, t, c, arg))
+    return out
+
+
+def sv_apply_circuit_ex(h, gates, sched: Optional[sv_schedule] = None) -> None:
+    arr, keep = ex_gates(gates)
+    _check(load().sv_apply_circuit_ex(h, arr, len(gates), ctypes.byref(sched) if sched is not None else None))
+    del keep
+
+
+def sv_qasm_parse(text: str):
+    """Parse OpenQASM 2.0 text: (number of qubits, gate tuples as ex_gates takes)."""
+    lib = load()
+    src = text.encode()
+    cnt = ctypes.c_size_t(0)
+    nq = ctypes.c_int(0)
+    _check(lib.sv_qasm_parse(src, None, 0, ctypes.byref(cnt), ctypes.byref(nq)))
+    arr = (sv_gate_ex * max(1, cnt.value))()
+    _check(lib.sv_qasm_parse(src, arr, cnt.value, ctypes.byref(cnt), ctypes.byref(nq)))
+    return nq.value, ex_tuples(arr, cnt.value)
+
+
 # ---------------------------------------------------------------- convenience
 
 class StateVector:
@@ -523,6 +611,10 @@ class StateVector:
 
     def apply(self, gates, sched: Optional[sv_schedule] = None):
         sv_apply_circuit(self.h, gates, sched)
+        return self
+
+    def apply_ex(self, gates, sched: Optional[sv_schedule] = None):
+        sv_apply_circuit_ex(self.h, gates, sched)
         return self
 
     def reset(self):
