@@ -279,24 +279,33 @@ sv_status sv_prepare(sv_handle h, const sv_gate *gates, size_t m, const sv_sched
 
 /* Many independent circuits, one per handle (all of one dtype, distinct
  * handles, one device), in one persistent kernel launch captured in a HIP
- * graph. Each instance is planned with the partitioned schedule at one shared
- * block size (the schedule's, capped by the smallest instance); work-groups
- * are split among instances in proportion to their work and run each
- * instance's passes in order, meeting at a device-scope counter barrier
- * between passes. The graph is cached by a hash of the gate lists, layouts,
- * buffers and schedule, so the same batch applied again replays it. Runs on
- * the first handle's stream and synchronizes it (the barrier's error flag is
+ * graph. The launch has one work-group size, 2^t threads with t = min(L - r,
+ * n_min - 3) for the schedule's block size L and register tile r (defaults:
+ * the dtype's block size and a tile one below the dtype's, 4 for complex64
+ * and 3 for complex128, which keeps two work-groups per CU); instance i is planned with the partitioned schedule at its
+ * own block size l_i = min(n_i, t + r) and tile l_i - t (at least 3), so
+ * large states use the full block and small ones shrink only their tile. An
+ * instance carrying at least two work-groups' share of the work gets that
+ * many work-groups (at most one per block), which meet at a device-scope
+ * counter barrier between passes; smaller instances are packed, largest
+ * first, onto the least loaded remaining work-groups and run there one after
+ * another. The graph is cached by a hash of the gate lists, layouts, buffers
+ * and schedule, so the same batch applied again replays it. Runs on the
+ * first handle's stream and synchronizes it (the barrier's error flag is
  * checked: SV_ERR_DEVICE if a barrier wait timed out). Schedules that are not
- * partitioned with virtual remap, or more instances than resident
- * work-groups, are applied one circuit after another. Each handle's stats
- * receive its own counts and the batch's device time. */
+ * partitioned with virtual remap, or a register tile outside 3..5 (3..4 for
+ * complex128), are applied one circuit after another. Each handle's stats
+ * receive its own counts, its block size and the batch's device time. */
 sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m,
                          const sv_schedule *s);
 
 /* Exhaustive batch tuner: times sv_apply_batch on scratch copies of the
- * states for every block size from the smallest instance size down three
- * qubits (at least 7) and diagonal-run combining off/on, and returns the
- * fastest schedule (median of three runs). The states are not changed. */
+ * states for the three largest block sizes (the largest is the dtype's
+ * maximum, capped by the largest instance; at least 7), register tiles of
+ * the dtype's default and one below, and fusion widths fuse_k 1, 4 and 5
+ * (matrix-core windows where the cost gate admits them), and returns the
+ * fastest schedule (median of three runs after a warm-up).
+ * The states are not changed. */
 sv_status sv_tune_batch(sv_handle *hs, int count, const sv_gate *const *gates, const size_t *m, sv_schedule *out);
 
 /* Probabilities |alpha|^2 in FP64 (measurement, the meters of the QPE

@@ -1499,7 +1499,7 @@ namespace {
 // of everything its plans depend on.
 struct BatchEntry {
     uint64_t key = 0;
-    int dtype = 0, logr = 4, count = 0;
+    int dtype = 0, lmax = 4, count = 0;
     unsigned grid = 0, threads = 0;
     size_t lds = 0;
     void *dbuf = nullptr;
@@ -1508,7 +1508,7 @@ struct BatchEntry {
     hipGraphExec_t exec = nullptr;
     std::vector<std::vector<int>> l2p_after;
     std::vector<svp::PlanStats> stats;
-    int l = 0;
+    std::vector<int> l;        // block qubits per instance
     ~BatchEntry()
     {
         if (exec) hipGraphExecDestroy(exec);
@@ -1554,15 +1554,29 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     svp::PlanConfig base = config_from(hs[0], s);
     int min_n = 64;
     for (int i = 0; i < count; ++i) min_n = std::min(min_n, hs[i]->n);
-    int l = base.l > 0 ? base.l : svp::default_block_qubits(dtype);
-    l = std::min(l, min_n);
-    const int logr = std::min(s && s->reg_qubits > 0 ? s->reg_qubits : 4, l);
-    if (base.mode != 1 || base.remap != 0 || logr < 3 || logr > 4) {
+    // One work-group size for the launch, 2^tbits threads; instance i runs
+    // blocks of l_i = min(n_i, tbits + rmax) qubits with a register tile of
+    // l_i - tbits (3 .. rmax) amplitude bits.
+    const int lreq = base.l > 0 ? base.l : svp::default_block_qubits(dtype);
+    // default tile: one below the single-state default (the batched kernel
+    // runs the interpreter, whose largest tile needs twice the registers and
+    // halves the resident work-groups)
+    const int rmax = std::min(s && s->reg_qubits > 0 ? s->reg_qubits : svp::default_reg_qubits(dtype) - 1, lreq);
+    if (base.mode != 1 || base.remap != 0 || rmax < 3 || rmax > (dtype == 0 ? 5 : 4) || min_n < 3) {
         *sequential = true;
         return nullptr;
     }
+    int tbits = std::min(lreq - rmax, min_n - 3);
+    while ((1 << tbits) > svk::k6_max_threads(dtype, rmax)) --tbits;
+    std::vector<int> li(count), ri(count);
+    int lmax_tile = 3;
+    for (int i = 0; i < count; ++i) {
+        li[i] = std::min(hs[i]->n, tbits + rmax);
+        ri[i] = li[i] - tbits;
+        lmax_tile = std::max(lmax_tile, ri[i]);
+    }
     uint64_t key = mix64(0x5eed, (uint64_t)count);
-    key = mix64(key, (uint64_t)l);
+    key = mix64(key, (uint64_t)tbits);
     key = hash_bytes(key, &base, sizeof(base));
     for (int i = 0; i < count; ++i) {
         key = mix64(key, (uint64_t)(uintptr_t)hs[i]->buf);
@@ -1580,12 +1594,12 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
                 return e;
             }
     }
-    // plan every instance with the shared block size
+    // plan every instance with its own block size and tile
     std::vector<svp::Plan> plans(count);
     for (int i = 0; i < count; ++i) {
         svp::PlanConfig c = config_from(hs[i], s);
-        c.l = l;
-        c.logr = logr;
+        c.l = li[i];
+        c.logr = ri[i];
         std::string e = svp::make_plan(c, reinterpret_cast<const svp::RawGate *>(gates[i]), m[i], hs[i]->l2p, plans[i]);
         if (!e.empty()) {
             *err = "instance " + std::to_string(i) + ": " + e;
@@ -1623,6 +1637,8 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
         insts[i].S = hs[i]->buf;
         insts[i].pass_off = (int)passes.size();
         insts[i].npass = 0;
+        insts[i].logr = ri[i];
+        insts[i].l = li[i];
         insts[i].ctr = i;
         for (const svp::Step &st : P.steps) {
             svp::BatchPass bp{};
@@ -1654,14 +1670,17 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
             passes.push_back(bp);
             insts[i].npass += 1;
         }
-        work[i] = (double)insts[i].npass * std::ldexp(1.0, hs[i]->n - l);
+        // work in amplitudes moved: every pass reads and writes the state
+        work[i] = (double)insts[i].npass * std::ldexp(1.0, hs[i]->n);
     }
-    // resident capacity and work-group groups
-    const unsigned threads = 1u << (l - logr);
-    const size_t lds = std::max<size_t>(max_lds, svp::k2_lds_layout(l, (int)amp, 0, 0, 0, all_half).total);
+    // resident capacity
+    const unsigned threads = 1u << tbits;
+    int lmax_blk = 0;
+    for (int x : li) lmax_blk = std::max(lmax_blk, x);
+    const size_t lds = std::max<size_t>(max_lds, svp::k2_lds_layout(lmax_blk, (int)amp, 0, 0, 0, all_half).total);
     bool mfma = false;
     for (const svp::K2Op &op : ops) mfma = mfma || op.kind == svp::K2_MFMA;
-    const int per_cu = svk::k6_occupancy(dtype, logr, threads, lds, mfma);
+    const int per_cu = svk::k6_occupancy(dtype, lmax_tile, threads, lds, mfma);
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1) {
@@ -1669,40 +1688,86 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
         return nullptr;
     }
     const long cap = (long)per_cu * cus;
-    if (count > cap) {
+    // Work-groups: an instance with more than one work-group's share of the
+    // work gets ceil(share) of its own (at most one per block; the largest
+    // groups shrink until everything fits the resident capacity); the
+    // others are packed, largest first, onto the least loaded of the
+    // remaining work-groups, one after another without barriers.
+    double wsum = 0;
+    for (double w : work) wsum += w;
+    const double target = wsum > 0 ? wsum / (double)cap : 1.0;
+    std::vector<int> gsz(count, 1);
+    for (int i = 0; i < count; ++i) {
+        const double blocks = std::ldexp(1.0, hs[i]->n - li[i]);
+        const double share = work[i] / target;
+        gsz[i] = share > 1.0 ? (int)std::min(std::ceil(share), blocks) : 1;
+    }
+    auto packing = [&](long *ded, long *bins, double *single_work, long *nsingle) {
+        *ded = 0;
+        *single_work = 0;
+        *nsingle = 0;
+        for (int i = 0; i < count; ++i) {
+            if (gsz[i] > 1) {
+                *ded += gsz[i];
+            } else {
+                *single_work += work[i];
+                *nsingle += 1;
+            }
+        }
+        *bins = *nsingle == 0 ? 0 : std::min(*nsingle, std::max(1L, (long)std::ceil(*single_work / target)));
+    };
+    long ded, bins, nsingle;
+    double single_work;
+    packing(&ded, &bins, &single_work, &nsingle);
+    while (ded + bins > cap) {
+        const int big = (int)(std::max_element(gsz.begin(), gsz.end()) - gsz.begin());
+        if (gsz[big] <= 1) break;
+        gsz[big] -= 1;
+        packing(&ded, &bins, &single_work, &nsingle);
+    }
+    if (ded + bins > cap) bins = cap - ded;
+    if (nsingle > 0 && bins < 1) {
         *sequential = true;
         return nullptr;
     }
-    double wsum = 0;
-    for (double w : work) wsum += w;
-    std::vector<int> gsz(count);
-    long total = 0;
+    std::vector<std::vector<std::pair<int, int>>> wg;  // per work-group: (instance, rank)
     for (int i = 0; i < count; ++i) {
-        const double blocks = std::ldexp(1.0, hs[i]->n - l);
-        double g = std::floor((double)cap * work[i] / wsum);
-        g = std::max(1.0, std::min(g, blocks));
-        gsz[i] = (int)g;
-        total += gsz[i];
-    }
-    while (total > cap) {
-        int big = (int)(std::max_element(gsz.begin(), gsz.end()) - gsz.begin());
-        gsz[big] -= 1;
-        total -= 1;
-    }
-    std::vector<int32_t> wg_inst;
-    for (int i = 0; i < count; ++i) {
-        insts[i].group_off = (int)wg_inst.size();
         insts[i].group_size = gsz[i];
-        for (int g = 0; g < gsz[i]; ++g) wg_inst.push_back(i);
+        if (gsz[i] > 1)
+            for (int r = 0; r < gsz[i]; ++r) wg.push_back({{i, r}});
     }
-    // one device buffer: insts | wg_inst | passes | ops | table | counters
+    {
+        std::vector<int> order;
+        for (int i = 0; i < count; ++i)
+            if (gsz[i] == 1) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+        std::vector<double> load(bins, 0.0);
+        const size_t first = wg.size();
+        wg.resize(first + bins);
+        for (int i : order) {
+            const size_t b = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[b] += work[i];
+            wg[first + b].push_back({i, 0});
+        }
+    }
+    std::vector<int32_t> wg_off(1, 0);
+    std::vector<int32_t> jobs;  // int2 pairs
+    for (const auto &w : wg) {
+        for (const auto &j : w) {
+            jobs.push_back(j.first);
+            jobs.push_back(j.second);
+        }
+        wg_off.push_back((int32_t)(jobs.size() / 2));
+    }
+    // one device buffer: insts | wg_off | jobs | passes | ops | table | counters
     BatchEntry *e = new (std::nothrow) BatchEntry();
     if (!e) {
         *err = "host allocation failed";
         return nullptr;
     }
     const size_t o_inst = 0, o_wg = align16(o_inst + insts.size() * sizeof(svp::BatchInst));
-    const size_t o_pass = align16(o_wg + wg_inst.size() * sizeof(int32_t));
+    const size_t o_jobs = align16(o_wg + wg_off.size() * sizeof(int32_t));
+    const size_t o_pass = align16(o_jobs + jobs.size() * sizeof(int32_t));
     const size_t o_ops = align16(o_pass + passes.size() * sizeof(svp::BatchPass));
     const size_t o_tab = align16(o_ops + ops.size() * sizeof(svp::K2Op));
     const size_t o_ctr = align16(o_tab + table.size());
@@ -1720,7 +1785,8 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
         if (he == hipSuccess && n) he = hipMemcpyAsync(d + off, src, n, hipMemcpyHostToDevice, st);
     };
     up(o_inst, insts.data(), insts.size() * sizeof(svp::BatchInst));
-    up(o_wg, wg_inst.data(), wg_inst.size() * sizeof(int32_t));
+    up(o_wg, wg_off.data(), wg_off.size() * sizeof(int32_t));
+    up(o_jobs, jobs.data(), jobs.size() * sizeof(int32_t));
     up(o_pass, passes.data(), passes.size() * sizeof(svp::BatchPass));
     up(o_ops, ops.data(), ops.size() * sizeof(svp::K2Op));
     up(o_tab, table.data(), table.size());
@@ -1728,12 +1794,12 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     e->ctrs = reinterpret_cast<unsigned *>(d + o_ctr);
     e->key = key;
     e->dtype = dtype;
-    e->logr = logr;
+    e->lmax = lmax_tile;
     e->count = count;
-    e->grid = (unsigned)wg_inst.size();
+    e->grid = (unsigned)wg.size();
     e->threads = threads;
     e->lds = lds;
-    e->l = l;
+    e->l = li;
     for (int i = 0; i < count; ++i) {
         e->l2p_after.push_back(plans[i].l2p_after);
         e->stats.push_back(plans[i].stats);
@@ -1746,9 +1812,9 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     if (he == hipSuccess) he = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
         hipError_t h1 = svk::zero_u32(e->ctrs, (uint32_t)(count + 1), cap_st);
-        hipError_t h2 = svk::k6_batch(dtype, logr, e->grid, threads, lds,
+        hipError_t h2 = svk::k6_batch(dtype, lmax_tile, e->grid, threads, lds,
                                       reinterpret_cast<const svp::BatchInst *>(d + o_inst),
-                                      reinterpret_cast<const int32_t *>(d + o_wg),
+                                      reinterpret_cast<const int32_t *>(d + o_wg), d + o_jobs,
                                       reinterpret_cast<const svp::BatchPass *>(d + o_pass),
                                       reinterpret_cast<const svp::K2Op *>(d + o_ops), e->ctrs,
                                       reinterpret_cast<int *>(e->ctrs + count), 1u << 24, mfma, cap_st);
@@ -1831,9 +1897,10 @@ sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, 
         h->st.swaps = e->stats[i].swaps;
         h->st.phases = e->stats[i].phases;
         h->st.passes = e->stats[i].passes;
+        h->st.fused = e->stats[i].fused;
         h->st.bytes = e->stats[i].bytes;
         h->st.device_ms = ms;
-        h->st.block_qubits = e->l;
+        h->st.block_qubits = e->l[i];
         h->st.mode = 1;
         h->st.fuse_k = s ? s->fuse_k : 1;
         h->st.swap_policy = s ? s->swap_policy : SV_SWAP_GRAPH;
@@ -1848,10 +1915,10 @@ sv_status sv_tune_batch(sv_handle *hs, int count, const sv_gate *const *gates, c
     if (!out) return fail(SV_ERR_INVALID_ARG, "out is null");
     if (count == 0) return fail(SV_ERR_INVALID_ARG, "empty batch");
     const int dtype = hs[0]->dtype;
-    int min_n = 64;
+    int max_n = 0;
     size_t total = 0;
     for (int i = 0; i < count; ++i) {
-        min_n = std::min(min_n, hs[i]->n);
+        max_n = std::max(max_n, hs[i]->n);
         total += align16(hs[i]->bytes);
     }
     // scratch copies of every state, wrapped in temporary handles
@@ -1871,12 +1938,17 @@ sv_status sv_tune_batch(sv_handle *hs, int count, const sv_gate *const *gates, c
     sv_schedule best{};
     double best_ms = 1e30;
     if (rc == SV_OK) {
-        const int lmax = std::min(min_n, svp::max_block_qubits(dtype));
-        for (int l = std::max(7, lmax - 3); l <= lmax && rc == SV_OK; ++l)
-            for (int fuse = 0; fuse <= 1 && rc == SV_OK; ++fuse) {
+        const int lmax = std::min(max_n, svp::max_block_qubits(dtype));
+        static const int fuse_ks[] = {1, 4, 5};
+        const int rdef = svp::default_reg_qubits(dtype);
+        for (int l = std::max(7, lmax - 2); l <= lmax && rc == SV_OK; ++l)
+            for (int r = rdef - 1; r <= rdef && rc == SV_OK; ++r)
+            for (int fuse : fuse_ks) {
+                if (rc != SV_OK) break;
                 sv_schedule c{};
                 c.mode = SV_PARTITIONED;
                 c.block_qubits = l;
+                c.reg_qubits = r;
                 c.fuse_k = fuse;
                 c.swap_policy = SV_SWAP_GRAPH;
                 c.remap = SV_REMAP_VIRTUAL;

@@ -158,16 +158,16 @@ constexpr int k2_canon_bit(int j, int l, int r)
 }
 
 // Batched passes (one persistent launch over many states). Instance i is
-// served by work-groups group_off .. group_off + group_size - 1, which run its
+// served by group_size work-groups (ranks 0 .. group_size-1), which run its
 // passes in order and meet at a counter barrier between passes.
 struct BatchInst {
     void *S;             // the instance's state
     int32_t npass;
     int32_t pass_off;    // first BatchPass of this instance
-    int32_t group_off;   // first work-group
+    int32_t logr;        // register tile (2^logr amplitudes per thread)
     int32_t group_size;  // work-groups sharing the instance
-    int32_t ctr;         // barrier counter index
-    int32_t pad;
+    int32_t ctr;         // barrier counter index (group_size > 1)
+    int32_t l;           // block qubits of its passes
 };
 struct BatchPass {
     K2Args args;         // args.table points to the batch table

@@ -385,10 +385,12 @@ __device__ __forceinline__ void k2_mfma(C *a, K2Ctx &cx, const int *rb, const in
     }
     const uint32_t nvec = 1u << (l - KW);
     const int groups = (int)((nvec + 15u) >> 4);
-    const T *M = static_cast<const T *>(mat);
     // The table address is laundered so that its loads stay inside this op:
     // they do not depend on the block, and hoisting every window's operands
-    // out of the block loop would need hundreds of registers.
+    // out of the block loop would need hundreds of registers. It is read as
+    // a uniform value first (it is one), so that the scalar-register operand
+    // holds wherever the compiler cannot prove it uniform by itself.
+    const T *M = reinterpret_cast<const T *>(uniform64(reinterpret_cast<uint64_t>(mat)));
     asm volatile("" : "+s"(M));
     // The lane's A operand for every (tile, step) of a 4-qubit window is
     // loaded once per op (16 or 32 registers) while the block's own registers

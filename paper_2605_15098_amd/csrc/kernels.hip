@@ -337,30 +337,64 @@ __device__ bool group_barrier(unsigned *ctr, unsigned target, int *err, unsigned
         *ok = good;
     }
     __syncthreads();
-    return *ok != 0;
+    // the same for every thread after the barrier: read as a uniform value,
+    // so that code after a barrier stays uniform for the compiler too
+    return __builtin_amdgcn_readfirstlane(*ok) != 0;
 }
 
-// Many states in one persistent launch: each work-group serves one instance
-// (wg_inst), runs every pass of that instance's program on its share of the
-// blocks, and waits for the instance's other work-groups between passes.
+// The passes of one instance on this work-group's share of its blocks
+// (rank among group_size work-groups). Work-groups that share an instance
+// meet at the counter barrier between passes; a work-group that runs an
+// instance alone meets its own waves there, since the next pass reads what
+// other waves stored.
 template <typename T, int LOGR, bool MFMA>
-__global__ void __launch_bounds__((k2_max_threads<T, LOGR>()))
-k6_batch_kernel(const svp::BatchInst *__restrict__ insts, const int32_t *__restrict__ wg_inst,
-                const svp::BatchPass *__restrict__ passes, const svp::K2Op *__restrict__ ops, unsigned *ctrs,
-                int *err, unsigned limit)
+__device__ bool k6_run(const svp::BatchInst &I, uint64_t rank, const svp::BatchPass *__restrict__ passes,
+                       const svp::K2Op *__restrict__ ops, unsigned *ctrs, int *err, unsigned limit,
+                       unsigned char *lds, int *ok)
 {
     using C = typename CT<T>::type;
-    extern __shared__ unsigned char lds_raw[];
-    __shared__ int ok;
-    const svp::BatchInst I = insts[wg_inst[blockIdx.x]];
-    const uint64_t rank = blockIdx.x - I.group_off;
     for (int p = 0; p < I.npass; ++p) {
         const svp::BatchPass &P = passes[I.pass_off + p];
-        k2_body_any<T, LOGR, K2Interp<MFMA>, MFMA ? 0 : 1>((C *)I.S, P.args, lds_raw,
-                                                            K2Interp<MFMA>{ops + P.op_begin, P.args.nops, P.args.l},
-                                                            rank, (uint64_t)I.group_size);
-        if (I.group_size > 1 && p + 1 < I.npass)
-            if (!group_barrier(&ctrs[I.ctr], (unsigned)((p + 1) * I.group_size), err, limit, &ok)) return;
+        k2_body_any<T, LOGR, K2Interp<MFMA>, 0>((C *)I.S, P.args, lds,
+                                                 K2Interp<MFMA>{ops + P.op_begin, P.args.nops, P.args.l}, rank,
+                                                 (uint64_t)I.group_size);
+        if (p + 1 == I.npass) break;
+        if (I.group_size > 1) {
+            if (!group_barrier(&ctrs[I.ctr], (unsigned)((p + 1) * I.group_size), err, limit, ok)) return false;
+        } else {
+            __syncthreads();
+        }
+    }
+    return true;
+}
+
+// Many states in one persistent launch. Work-group w runs the jobs
+// wg_off[w] .. wg_off[w+1]-1 in order; a job is (instance, rank). An
+// instance spread over several work-groups is their only job; small
+// instances are packed several to a work-group. Every instance uses the
+// launch's work-group size: its block has l = r + log2(threads) local qubits
+// with its own register tile r (I.logr, 3 .. LMAX), so a small state runs
+// with smaller tiles instead of shrinking every instance's block.
+template <typename T, int LMAX, bool MFMA>
+__global__ void __launch_bounds__((k2_max_threads<T, LMAX>()))
+k6_batch_kernel(const svp::BatchInst *__restrict__ insts, const int32_t *__restrict__ wg_off,
+                const int2 *__restrict__ jobs, const svp::BatchPass *__restrict__ passes,
+                const svp::K2Op *__restrict__ ops, unsigned *ctrs, int *err, unsigned limit)
+{
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ int ok;
+    const int j0 = wg_off[blockIdx.x], j1 = wg_off[blockIdx.x + 1];
+    for (int j = j0; j < j1; ++j) {
+        if (j > j0) __syncthreads();  // the previous job's last reads of LDS
+        const int2 J = jobs[j];
+        const svp::BatchInst I = insts[J.x];
+        bool good = true;
+        if (I.logr == 3) good = k6_run<T, 3, MFMA>(I, (uint64_t)J.y, passes, ops, ctrs, err, limit, lds_raw, &ok);
+        if constexpr (LMAX >= 4)
+            if (I.logr == 4) good = k6_run<T, 4, MFMA>(I, (uint64_t)J.y, passes, ops, ctrs, err, limit, lds_raw, &ok);
+        if constexpr (LMAX >= 5)
+            if (I.logr == 5) good = k6_run<T, 5, MFMA>(I, (uint64_t)J.y, passes, ops, ctrs, err, limit, lds_raw, &ok);
+        if (!good) return;
     }
 }
 
@@ -376,20 +410,29 @@ hipError_t zero_u32(unsigned *p, uint32_t n, hipStream_t st)
 }
 
 template <typename T>
-static const void *k6_fn(int logr, bool mfma)
+static const void *k6_fn(int lmax, bool mfma)
 {
-    switch (logr * 2 + (mfma ? 1 : 0)) {
+    switch (lmax * 2 + (mfma ? 1 : 0)) {
     case 6: return (const void *)k6_batch_kernel<T, 3, false>;
     case 7: return (const void *)k6_batch_kernel<T, 3, true>;
     case 8: return (const void *)k6_batch_kernel<T, 4, false>;
     case 9: return (const void *)k6_batch_kernel<T, 4, true>;
+    case 10: return (const void *)k6_batch_kernel<T, 5, false>;
+    case 11: return (const void *)k6_batch_kernel<T, 5, true>;
     default: return nullptr;
     }
 }
 
-int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds, bool mfma)
+int k6_max_threads(int dtype, int lmax)
 {
-    const void *fn = dtype == 0 ? k6_fn<float>(logr, mfma) : k6_fn<double>(logr, mfma);
+    if (lmax < 3 || lmax > 5) return 0;
+    const int bumped = lmax + (dtype == 0 ? 0 : 1);
+    return bumped >= 5 ? (bumped >= 6 ? 256 : 512) : 1024;
+}
+
+int k6_occupancy(int dtype, int lmax, unsigned threads, size_t lds, bool mfma)
+{
+    const void *fn = dtype == 0 ? k6_fn<float>(lmax, mfma) : k6_fn<double>(lmax, mfma);
     if (!fn) return 0;
     if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
@@ -398,13 +441,13 @@ int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds, bool mfma)
     return per_cu;
 }
 
-hipError_t k6_batch(int dtype, int logr, unsigned grid, unsigned threads, size_t lds, const svp::BatchInst *insts,
-                    const int32_t *wg_inst, const svp::BatchPass *passes, const svp::K2Op *ops, unsigned *ctrs,
-                    int *err, unsigned limit, bool mfma, hipStream_t st)
+hipError_t k6_batch(int dtype, int lmax, unsigned grid, unsigned threads, size_t lds, const svp::BatchInst *insts,
+                    const int32_t *wg_off, const void *jobs, const svp::BatchPass *passes, const svp::K2Op *ops,
+                    unsigned *ctrs, int *err, unsigned limit, bool mfma, hipStream_t st)
 {
-    const void *fn = dtype == 0 ? k6_fn<float>(logr, mfma) : k6_fn<double>(logr, mfma);
+    const void *fn = dtype == 0 ? k6_fn<float>(lmax, mfma) : k6_fn<double>(lmax, mfma);
     if (!fn) return hipErrorInvalidValue;
-    void *args[] = {&insts, &wg_inst, &passes, &ops, &ctrs, &err, &limit};
+    void *args[] = {&insts, &wg_off, &jobs, &passes, &ops, &ctrs, &err, &limit};
     return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, st);
 }
 

@@ -23,11 +23,14 @@ hipError_t to_storage_order(void *S, int n, int dtype, hipStream_t st);
 // Batched passes: see k6_batch_kernel. grid must not exceed the resident
 // capacity (k6_occupancy work-groups per CU times the CU count) so that the
 // work-groups of one instance can wait for each other.
-// mfma: some pass runs matrix-core windows (selects that build of the kernel).
-int k6_occupancy(int dtype, int logr, unsigned threads, size_t lds, bool mfma);
-hipError_t k6_batch(int dtype, int logr, unsigned grid, unsigned threads, size_t lds, const svp::BatchInst *insts,
-                    const int32_t *wg_inst, const svp::BatchPass *passes, const svp::K2Op *ops, unsigned *ctrs,
-                    int *err, unsigned limit, bool mfma, hipStream_t st);
+// lmax: the largest register tile of any instance (3..5; selects the
+// build); mfma: some pass runs matrix-core windows. jobs: int2 (instance,
+// rank) records, work-group w running wg_off[w] .. wg_off[w+1]-1.
+int k6_max_threads(int dtype, int lmax);
+int k6_occupancy(int dtype, int lmax, unsigned threads, size_t lds, bool mfma);
+hipError_t k6_batch(int dtype, int lmax, unsigned grid, unsigned threads, size_t lds, const svp::BatchInst *insts,
+                    const int32_t *wg_off, const void *jobs, const svp::BatchPass *passes, const svp::K2Op *ops,
+                    unsigned *ctrs, int *err, unsigned limit, bool mfma, hipStream_t st);
 hipError_t zero_u32(unsigned *p, uint32_t n, hipStream_t st);
 hipError_t k1_gate(void *S, int n, int dtype, const svp::MGate &g, hipStream_t st);
 hipError_t k3_swap(void *S, int n, int dtype, int p, int v, hipStream_t st);

@@ -79,7 +79,8 @@ def test_batch_tuner_leaves_states():
     before = [s.state() for s in batch]
     log("case batch tuner")
     best = sv.sv_tune_batch([s.h for s in batch], gl)
-    assert best.mode == sv.SV_PARTITIONED and 7 <= best.block_qubits <= 12
+    # block sizes: the three largest up to the largest instance; fusion 1, 4 or 5
+    assert best.mode == sv.SV_PARTITIONED and 12 <= best.block_qubits <= 14 and best.fuse_k in (1, 4, 5)
     for s, b in zip(batch, before):
         assert np.array_equal(s.state(), b)
     sv.sv_apply_batch([s.h for s in batch], gl, best)
@@ -125,5 +126,99 @@ def test_batch_256_instances_config():
             got = sv.sv_state_range(s.h, (1 << t) + a, 512, "c64").astype(np.complex128)
             worst = max(worst, float(np.max(np.abs(got - cf.qpe_amplitudes(t, p, np.arange(a, a + 512))))))
     assert worst <= 2e-5, worst
+    for s in batch:
+        s.close()
+
+
+def launch_tbits(dtype, ns, block_qubits=0, reg_qubits=0):
+    """log2 of the batch launch's work-group size, as sv_apply_batch sizes it."""
+    lreq = block_qubits or (14 if dtype == "c64" else 13)
+    rmax = min(reg_qubits or (4 if dtype == "c64" else 3), lreq)
+    tbits = min(lreq - rmax, min(ns) - 3)
+    max_threads = {("c64", 3): 1024, ("c64", 4): 1024, ("c64", 5): 512,
+                   ("c128", 3): 1024, ("c128", 4): 512}[(dtype, rmax)]
+    # (a smaller tile than rmax for every instance selects a build that
+    # allows at least as many threads)
+    while (1 << tbits) > max_threads:
+        tbits -= 1
+    return tbits
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_per_instance_block_sizes(dtype):
+    """Default schedule: each instance runs its own block size (the full
+    block for large states, a smaller register tile for small ones) and
+    equals the single run with that block size and tile, bit for bit."""
+    rng = np.random.default_rng(46)
+    ns = [12, 13, 14, 15, 17, 19, 12, 20]
+    phis = [float(x) for x in rng.random(len(ns))]
+    gl = [W.qpe_gates(n, p) for n, p in zip(ns, phis)]
+    batch = make(ns, dtype)
+    log(f"case batch per-instance blocks dtype={dtype}")
+    sv.sv_apply_batch([s.h for s in batch], gl)
+    tb = launch_tbits(dtype, ns)
+    lmax = 14 if dtype == "c64" else 13
+    rmax = 4 if dtype == "c64" else 3
+    for i, (n, p) in enumerate(zip(ns, phis)):
+        l = batch[i].stats()["block_qubits"]
+        assert l == min(n, tb + rmax) and l <= lmax
+        single = sv.StateVector(n, dtype)
+        single.apply(gl[i], sv.schedule(block_qubits=l, reg_qubits=l - tb))
+        a, b = batch[i].state(), single.state()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (i, n, l)
+        assert np.max(np.abs(a - cf.qpe_state(n, p))) <= TOL[dtype]
+        single.close()
+    for s in batch:
+        s.close()
+
+
+def test_batch_packs_small_instances_onto_shared_work_groups():
+    """A few large states and many small ones: the small ones share
+    work-groups and run one after another (several passes each, with the
+    work-group's own barrier between passes)."""
+    rng = np.random.default_rng(47)
+    ns = [20, 21, 20, 21] + [int(x) for x in rng.integers(12, 15, size=90)]
+    phis = [float(x) for x in rng.random(len(ns))]
+    gl = [W.qpe_gates(n, p) for n, p in zip(ns, phis)]
+    batch = make(ns, "c64")
+    log("case batch packing")
+    for rep in range(2):  # the second call replays the cached graph on the results
+        sv.sv_apply_batch([s.h for s in batch], gl)
+    tb = launch_tbits("c64", ns)
+    for i, (n, p) in enumerate(zip(ns, phis)):
+        l = batch[i].stats()["block_qubits"]
+        if i < 8 or i % 9 == 0:
+            single = sv.StateVector(n, "c64")
+            for _ in range(2):
+                single.apply(gl[i], sv.schedule(block_qubits=l, reg_qubits=l - tb))
+            a, b = batch[i].state(), single.state()
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (i, n, l)
+            single.close()
+    # one pass of QPE from |0>: every instance against the closed form
+    for s in batch:
+        s.reset()
+    sv.sv_apply_batch([s.h for s in batch], gl)
+    for s, (n, p) in zip(batch, zip(ns, phis)):
+        assert np.max(np.abs(s.state() - cf.qpe_state(n, p))) <= 2e-5
+    for s in batch:
+        s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_with_matrix_core_windows(dtype):
+    """Dense layered circuits with fuse_k = 5: windows run through the
+    batched kernel's matrix-core build; every instance against the oracle."""
+    import oracle
+    rng = np.random.default_rng(48)
+    ns = [12, 13, 14, 16]
+    gl = [W.layered_dense_circuit(n, 3, rng) for n in ns]
+    batch = make(ns, dtype)
+    log(f"case batch windows dtype={dtype}")
+    sched = sv.schedule(fuse_k=5)
+    sv.sv_apply_batch([s.h for s in batch], gl, sched)
+    fused = sum(s.stats()["fused"] for s in batch)
+    for s, n, g in zip(batch, ns, gl):
+        assert np.max(np.abs(s.state() - oracle.apply(n, g))) <= TOL[dtype]
+    assert fused > 0
     for s in batch:
         s.close()
