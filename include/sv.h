@@ -46,6 +46,8 @@
  *   SV_TRACE_HOST       print host-side upload and launch timings to stderr
  *   SV_K2_MAX_GRID      at most this many work-groups per block-pass launch
  *                       (each walks more blocks; same bits; tests)
+ *   SV_BATCH_MAX_GRID   at most this many work-groups in a batched launch
+ *                       (default: the resident capacity; same bits)
  */
 #ifndef SVMI_SV_H_INCLUDED
 #define SVMI_SV_H_INCLUDED
@@ -300,7 +302,7 @@ sv_status sv_apply_batch(sv_handle *hs, int count, const sv_gate *const *gates, 
                          const sv_schedule *s);
 
 /* Exhaustive batch tuner: times sv_apply_batch on scratch copies of the
- * states for the three largest block sizes (the largest is the dtype's
+ * states for the six largest block sizes (the largest is the dtype's
  * maximum, capped by the largest instance; at least 7), register tiles of
  * the dtype's default and one below, and fusion widths fuse_k 1, 4 and 5
  * (matrix-core windows where the cost gate admits them), and returns the

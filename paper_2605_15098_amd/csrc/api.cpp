@@ -1577,6 +1577,7 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
     }
     uint64_t key = mix64(0x5eed, (uint64_t)count);
     key = mix64(key, (uint64_t)tbits);
+    if (const char *env = std::getenv("SV_BATCH_MAX_GRID")) key = mix64(key, (uint64_t)std::atol(env));
     key = hash_bytes(key, &base, sizeof(base));
     for (int i = 0; i < count; ++i) {
         key = mix64(key, (uint64_t)(uintptr_t)hs[i]->buf);
@@ -1687,7 +1688,11 @@ BatchEntry *get_batch(sv_handle *hs, int count, const sv_gate *const *gates, con
         *err = "cannot size the batch launch";
         return nullptr;
     }
-    const long cap = (long)per_cu * cus;
+    long cap = (long)per_cu * cus;
+    if (const char *env = std::getenv("SV_BATCH_MAX_GRID")) {
+        const long v = std::atol(env);
+        if (v > 0) cap = std::min(cap, v);
+    }
     // Work-groups: an instance with more than one work-group's share of the
     // work gets ceil(share) of its own (at most one per block; the largest
     // groups shrink until everything fits the resident capacity); the
@@ -1941,7 +1946,7 @@ sv_status sv_tune_batch(sv_handle *hs, int count, const sv_gate *const *gates, c
         const int lmax = std::min(max_n, svp::max_block_qubits(dtype));
         static const int fuse_ks[] = {1, 4, 5};
         const int rdef = svp::default_reg_qubits(dtype);
-        for (int l = std::max(7, lmax - 2); l <= lmax && rc == SV_OK; ++l)
+        for (int l = std::max(7, lmax - 5); l <= lmax && rc == SV_OK; ++l)
             for (int r = rdef - 1; r <= rdef && rc == SV_OK; ++r)
             for (int fuse : fuse_ks) {
                 if (rc != SV_OK) break;

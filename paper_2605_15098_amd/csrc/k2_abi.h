@@ -150,7 +150,7 @@ inline K2Lds k2_lds_layout(int l, int amp, int nug, int tab_count, int nut, int 
 // lets most re-layouts split the block by it into halves of whole waves. A
 // block of r bits is all registers.
 #if defined(__HIPCC_RTC__) || defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
-__host__ __device__
+__host__ __device__ __attribute__((always_inline))
 #endif
 constexpr int k2_canon_bit(int j, int l, int r)
 {

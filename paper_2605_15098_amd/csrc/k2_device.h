@@ -513,22 +513,46 @@ __device__ __forceinline__ void k2_diagrun(C *a, const K2Ctx &cx, const svp::Dia
     const int ng = rec->ngroups;
     const double2 *qt = reinterpret_cast<const double2 *>(gs + ng);
     const uint32_t kmask = rec->kmask, qmask = rec->qmask;
+    // The groups are stored by ascending top register bit (rmask = 0 first),
+    // so one walk over them in record order hands every slot its factors in
+    // the order the record defines: a group whose top bit is not in k has
+    // rmask outside k and is skipped for that slot.
+    if constexpr (sizeof(C) * R <= 128) {
+        // each group's factor once per block, folded into every slot it covers
+        C T[R];
+        bool have[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        if (!((kmask >> k) & 1u)) continue;
-        C T = mk<C>(1.0, 0.0);
-        bool have = false;
-        for (int b = -1; b < LOGR; ++b) {
-            if (b >= 0 && !((k >> b) & 1)) continue;
+        for (int k = 0; k < R; ++k) {
+            T[k] = mk<C>(1.0, 0.0);
+            have[k] = false;
+        }
+        for (int i = 0; i < ng; ++i) {
+            const int rm = gs[i].rmask;
+            const C f = k2_group_factor<C>(gs[i], cx);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (!((kmask >> k) & 1u) || (rm & ~k)) continue;
+                T[k] = k2_fold(!have[k], T[k], f);
+                have[k] = true;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if ((kmask >> k) & 1u) k2_diag_apply(a[k], ((qmask >> k) & 1u) != 0, qt[k], have[k], T[k]);
+    } else {
+        // larger tiles: slot by slot (the accumulators would not fit)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (!((kmask >> k) & 1u)) continue;
+            C T = mk<C>(1.0, 0.0);
+            bool have = false;
             for (int i = 0; i < ng; ++i) {
-                const int rm = gs[i].rmask;
-                const int top = rm ? 31 - __builtin_clz((uint32_t)rm) : -1;
-                if (top != b || (rm & ~k)) continue;
+                if (gs[i].rmask & ~k) continue;
                 T = k2_fold(!have, T, k2_group_factor<C>(gs[i], cx));
                 have = true;
             }
+            k2_diag_apply(a[k], ((qmask >> k) & 1u) != 0, qt[k], have, T);
         }
-        k2_diag_apply(a[k], ((qmask >> k) & 1u) != 0, qt[k], have, T);
     }
 }
 

@@ -317,7 +317,7 @@ k2_kernel(typename CT<T>::type *__restrict__ S, const svp::K2Op *__restrict__ op
 // count reaches `target`; a wait that exceeds `limit` polls, or an error
 // raised by another group, sets *err and makes every waiter leave, so the
 // grid always drains.
-__device__ bool group_barrier(unsigned *ctr, unsigned target, int *err, unsigned limit, int *ok)
+__device__ __forceinline__ bool group_barrier(unsigned *ctr, unsigned target, int *err, unsigned limit, int *ok)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -348,13 +348,15 @@ __device__ bool group_barrier(unsigned *ctr, unsigned target, int *err, unsigned
 // instance alone meets its own waves there, since the next pass reads what
 // other waves stored.
 template <typename T, int LOGR, bool MFMA>
-__device__ bool k6_run(const svp::BatchInst &I, uint64_t rank, const svp::BatchPass *__restrict__ passes,
+__device__ __forceinline__ bool k6_run(const svp::BatchInst &I, uint64_t rank, const svp::BatchPass *__restrict__ passes,
                        const svp::K2Op *__restrict__ ops, unsigned *ctrs, int *err, unsigned limit,
                        unsigned char *lds, int *ok)
 {
     using C = typename CT<T>::type;
     for (int p = 0; p < I.npass; ++p) {
         const svp::BatchPass &P = passes[I.pass_off + p];
+        // no prefetch of the next block: measured no faster here, and its
+        // registers would push the interpreter into spills
         k2_body_any<T, LOGR, K2Interp<MFMA>, 0>((C *)I.S, P.args, lds,
                                                  K2Interp<MFMA>{ops + P.op_begin, P.args.nops, P.args.l}, rank,
                                                  (uint64_t)I.group_size);

@@ -79,8 +79,8 @@ def test_batch_tuner_leaves_states():
     before = [s.state() for s in batch]
     log("case batch tuner")
     best = sv.sv_tune_batch([s.h for s in batch], gl)
-    # block sizes: the three largest up to the largest instance; fusion 1, 4 or 5
-    assert best.mode == sv.SV_PARTITIONED and 12 <= best.block_qubits <= 14 and best.fuse_k in (1, 4, 5)
+    # block sizes: the six largest up to the largest instance; fusion 1, 4 or 5
+    assert best.mode == sv.SV_PARTITIONED and 9 <= best.block_qubits <= 14 and best.fuse_k in (1, 4, 5)
     for s, b in zip(batch, before):
         assert np.array_equal(s.state(), b)
     sv.sv_apply_batch([s.h for s in batch], gl, best)
