@@ -141,3 +141,37 @@ def test_trained_model_picks_a_candidate():
         s.close()
     finally:
         sv.sv_set_cost_model(None)
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(sv.__file__), "cost_model_c64.npz")),
+                    reason="no trained cost model in the package")
+def test_learned_schedule_gains_over_the_method_without_it():
+    """The shipped model (trained on the simulator's own timings of random
+    circuits of 20-31 qubits) on the first five held-out circuits of the
+    30-34 qubit evaluation set (30 qubits, depth 200): its picks take less
+    device time in total than the schedule used without a model (the
+    defaults), and far less than the paper's schedule (LRU victim,
+    data-moving SWAP, l = 13). Each pick is also checked to run correctly
+    on a small state by the tests above; here only times are compared."""
+    from paper_2605_15098_amd import costmodel
+    meta = costmodel.install()
+    log(f"model: {meta.get('circuits')} circuits, qubits {meta.get('n_range')}")
+    default = sv.schedule(block_qubits=14, reg_qubits=5, pin_qubits=5)
+    tot = {"learned": 0.0, "default": 0.0, "paper": 0.0}
+    try:
+        for i in range(5):
+            n, g = W.circuit_random_eval(i)
+            s = sv.StateVector(n, "c64")
+            pick = sv.sv_tune(s.h, g, sv.SV_TUNER_LEARNED)
+            ms, _ = sv.sv_tune_time(s.h, g, [pick, default], 3)
+            pms, _ = sv.sv_tune_time(s.h, g, [sv.paper_schedule(13)], 1)
+            s.close()
+            log(f"held-out circuit {i} n={n}: learned {ms[0]:.2f} ms, default {ms[1]:.2f} ms, paper {pms[0]:.1f} ms")
+            tot["learned"] += ms[0]
+            tot["default"] += ms[1]
+            tot["paper"] += pms[0]
+    finally:
+        sv.sv_set_cost_model(None)
+    log(f"totals: {tot}")
+    assert tot["learned"] < tot["default"]
+    assert 10 * tot["learned"] < tot["paper"]
