@@ -413,6 +413,53 @@ def bench_batch(steps):
     return res
 
 
+def bench_dense_fusion(steps, n=28, cases=(("blocked-depth24", 24),)):
+    """Matrix-core windows where the circuit is dense: circuits that keep
+    `depth` layers of RX and RY on every qubit with CZ along 5-qubit groups
+    before coupling the groups (two rounds; workloads.blocked_dense_circuit),
+    or, for depth 0, layers of rotations with CNOT ladders over all qubits
+    (about ten dense gates per window: the cost gate admits none). fuse_k 5
+    (windows through the matrix cores where the measured cost gate admits
+    them) against fuse_k 1, in both precisions: device time per circuit,
+    passes, gates taken into windows, and the largest amplitude difference
+    between the fused and unfused final states (both from |0>)."""
+    import torch
+    from paper_2605_15098_amd import sv
+    from paper_2605_15098_amd import workloads as W
+
+    res = {"n": n}
+    for name, depth in cases:
+        rng = np.random.default_rng(depth)
+        gates = (W.blocked_dense_circuit(n, 2, depth, rng) if depth > 0
+                 else W.layered_dense_circuit(n, 4, rng))
+        res[name] = {"gates": int(len(gates))}
+        for dt in ("c64", "c128"):
+            sims, row = {}, {}
+            for fuse in (1, 5):
+                sched = sv.schedule(fuse_k=fuse)
+                s = sv.StateVector(n, dt)
+                wall, dms, _, _, st = time_apply(s, gates, sched, steps, 1)
+                s.reset()
+                s.apply(gates, sched)
+                row[f"fuse_k{fuse}"] = {"ms_per_circuit": 1000.0 * wall / steps, "device_ms": dms / steps,
+                                        "passes": st["passes"], "gates_in_windows": st["fused"]}
+                sims[fuse] = s
+            diff = 0.0
+            chunk = 1 << 24
+            for o in range(0, 1 << n, chunk):
+                a = sv.sv_state_range(sims[1].h, o, chunk, dt).astype(np.complex128)
+                b = sv.sv_state_range(sims[5].h, o, chunk, dt).astype(np.complex128)
+                diff = max(diff, float(np.max(np.abs(a - b))))
+            for s in sims.values():
+                s.close()
+            torch.cuda.empty_cache()
+            row["speedup_fused"] = row["fuse_k1"]["ms_per_circuit"] / row["fuse_k5"]["ms_per_circuit"]
+            row["max_abs_diff_fused_vs_unfused"] = diff
+            res[name][dt] = row
+            log(f"dense fusion {name} {dt}: {row}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +481,8 @@ def main():
                     help="only run the paper's experiment: QPE with phi = 2^-t over n and block sizes")
     ap.add_argument("--sweep-precompile", metavar="DIR",
                     help="compile the sweep's passes into DIR on the host and exit (no GPU)")
+    ap.add_argument("--only", choices=("batch", "dense-fusion"),
+                    help="run only that section (batched QPE or dense-circuit fusion) and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 4 GiB read + 4 GiB write kernel "
                          "(the reference for HBM byte counters)")
@@ -447,6 +496,17 @@ def main():
         return
     if args.sweep_precompile:
         print(json.dumps({"precompiled": sweep_precompile(args.sweep_precompile)}), flush=True)
+        return
+    if args.only:
+        import torch
+        from paper_2605_15098_amd import sv
+
+        sv.load()
+        torch.cuda.set_device(0)
+        rec = (bench_batch(args.steps) if args.only == "batch" else
+               bench_dense_fusion(args.steps, cases=(("layered-depth1", 0), ("blocked-depth8", 8),
+                                                     ("blocked-depth12", 12), ("blocked-depth24", 24))))
+        print(json.dumps(rec), flush=True)
         return
     if args.sweep:
         import torch
@@ -575,6 +635,7 @@ def main():
         ref.drop()
     if not args.quick:
         out["batch_qpe256"] = bench_batch(args.steps)
+        out["dense_fusion"] = bench_dense_fusion(2)
     if not args.quick and not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(n, phi)

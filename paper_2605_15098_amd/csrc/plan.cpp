@@ -578,14 +578,21 @@ struct Builder {
             };
             // vector-ALU work per amplitude of a gate in a block pass, in
             // instructions (a 2x2 product: 8; controlled: half; Hadamard: 2;
-            // exchange: 1; a diagonal gate, folded into a run: 1), and of a
-            // matrix-core window: 4 * 2^k real multiply-adds per amplitude at
-            // twice (FP32) or once (FP64) the vector rate, plus its LDS round trip
+            // exchange: 1; a diagonal gate, folded into a run: 1), and the
+            // measured cost of a matrix-core window in the same units. The
+            // window's 2^k x 2^k product is 8 * 2^k flop per amplitude, at the
+            // vector rate on this GPU for FP32 and FP64 alike, plus two LDS
+            // round trips of the block and operand reads. Set from circuits
+            // that keep D layers of dense gates inside 5-qubit groups (28
+            // qubits, two rounds, windows growing across rounds): complex128
+            // windows won only at D = 8 and complex64 windows lost at every
+            // depth up to 8, so a 5-qubit window needs about 780 units of
+            // replaced work in complex128 and about 1540 in complex64.
             auto valu = [&](const MGate &g) {
                 double c = g.cls == GC_DIAG ? 1.0 : (g.cls == GC_PERM ? 1.0 : (g.op == 0 ? 2.0 : 8.0));
                 return g.c >= 0 && g.cls != GC_DIAG ? 0.5 * c : c;
             };
-            auto mfma_cost = [&](int k) { return (4 << k) / (cfg.dtype == 0 ? 2.0 : 1.0) + 8.0; };
+            auto mfma_cost = [&](int k) { return (double)((cfg.dtype == 0 ? 48 : 24) << k) + 8.0; };
             std::vector<MGate> rest(q.begin(), q.end());
             size_t pos = 0;
             while (pos < rest.size()) {

@@ -184,6 +184,29 @@ def layered_dense_circuit(n: int, layers: int, rng) -> np.ndarray:
     return gates_from_tuples(rows)
 
 
+def blocked_dense_circuit(n: int, rounds: int, depth: int, rng, group: int = 5) -> np.ndarray:
+    """Dense work that stays inside aligned groups of `group` qubits for
+    `depth` layers before the groups are coupled: per round, every group gets
+    `depth` layers of RX and RY on each of its qubits and CZ along the group,
+    then CNOT joins the last qubit of each group to the first of the next.
+    A group's layers form one run of 2 * group * depth dense gates on group
+    qubits, the shape a fused 2^group x 2^group window replaces."""
+    rows: List[Tuple] = []
+    starts = list(range(0, n, group))
+    for _ in range(rounds):
+        for g0 in starts:
+            qs = list(range(g0, min(n, g0 + group)))
+            for _ in range(depth):
+                for q in qs:
+                    rows.append(("RX", q, -1, float(rng.random() * 2.0 * math.pi)))
+                    rows.append(("RY", q, -1, float(rng.random() * 2.0 * math.pi)))
+                for a, b in zip(qs[:-1], qs[1:]):
+                    rows.append(("Z", b, a, 0.0))
+        for g0 in starts[1:]:
+            rows.append(("X", g0, g0 - 1, 0.0))
+    return gates_from_tuples(rows)
+
+
 def random_u2(rng) -> np.ndarray:
     """A Haar-ish random 2x2 unitary as the 8-double (re, im) row-major record."""
     z = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))

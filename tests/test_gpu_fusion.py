@@ -6,7 +6,8 @@ the QPE closed form, exact QPE argmax; compiled and interpreted passes agree
 bit for bit (same handler, same instruction order). The matrix-core path is
 exercised with SV_FUSE_ALL=1 (every window of 4 or 5 qubits, whatever its
 cost); the default cost gate is checked on the QPE (no window qualifies:
-the same bits as fuse_k 1) and on layered dense circuits (windows qualify).
+the same bits as fuse_k 1) and on deep dense runs inside 5-qubit groups
+(windows qualify).
 """
 import sys
 
@@ -116,15 +117,16 @@ def test_cost_gate_qpe_unfused_bits(dtype):
     assert np.max(np.abs(outs[0] - cf.qpe_state(n, phi))) <= TOL[dtype]
 
 
-@pytest.mark.parametrize("dtype,k", [("c64", 5), ("c64", 4), ("c128", 4)])
-def test_cost_gated_windows_on_layered_dense_circuit(dtype, k):
-    """Layers of RX/RY on every qubit and CNOT ladders: windows qualify under
-    the default cost gate and the fused state matches the oracle."""
+@pytest.mark.parametrize("dtype,depth", [("c64", 24), ("c128", 12)])
+def test_cost_gated_windows_on_deep_dense_groups(dtype, depth):
+    """Dense runs kept inside 5-qubit groups for `depth` layers: windows
+    qualify under the default (measured) cost gate and the fused state
+    matches the oracle."""
     n = 18
-    rng = np.random.default_rng(18 + k)
-    g = W.layered_dense_circuit(n, 8, rng)
+    rng = np.random.default_rng(18 + depth)
+    g = W.blocked_dense_circuit(n, 1, depth, rng)
     want = oracle.apply(n, g)
-    log(f"case cost-gated dense dtype={dtype} k={k}")
-    got, st = run(n, dtype, g, sv.schedule(block_qubits=12 if dtype == "c64" else 11, fuse_k=k))
+    log(f"case cost-gated dense dtype={dtype} depth={depth}")
+    got, st = run(n, dtype, g, sv.schedule(block_qubits=12 if dtype == "c64" else 11, fuse_k=5))
     assert st["fused"] > 0
     assert np.max(np.abs(got - want)) <= TOL[dtype]

@@ -167,29 +167,32 @@ def test_dense_fusion_programs(n, l, dtype, fuse, policy, monkeypatch):
 
 def test_window_cost_gate():
     """Without SV_FUSE_ALL a window is emitted only when its gates' estimated
-    vector-ALU work exceeds the matrix-core cost: the QPE's windows (a
-    Hadamard and phases per qubit) never qualify, so fuse_k 5 plans exactly
-    the fuse_k 1 program; layers of dense rotations over neighbouring qubits
-    do qualify, and every window has 4 or 5 qubits of its own."""
+    vector-ALU work exceeds the measured matrix-core cost: the QPE's windows
+    (a Hadamard and phases per qubit) and layers of rotations with CNOT
+    ladders (about ten dense gates per window) never qualify, so fuse_k 5
+    plans exactly the fuse_k 1 program; dense runs that stay inside 5-qubit
+    groups qualify from 12 layers in complex128 and 24 in complex64 (not at
+    8 and 12); every window has 4 or 5 qubits of its own."""
     n, l = 20, 13
     phi = W.phi_for_seed(7)
     g = W.qpe_gates(n, phi)
+    layered = W.layered_dense_circuit(n, 6, np.random.default_rng(3))
     for dt in ("c64", "c128"):
-        a = sv.sv_plan(n, dt, g, sv.schedule(block_qubits=l, fuse_k=5))
-        b = sv.sv_plan(n, dt, g, sv.schedule(block_qubits=l, fuse_k=1))
-        assert a["fused"] == 0 and a["passes"] == b["passes"]
-    dense = W.layered_dense_circuit(n, 6, np.random.default_rng(3))
-    # FP64 matrix cores run at half the FP32 rate: complex128 qualifies at k = 4
-    for dt, k in (("c64", 5), ("c64", 4), ("c128", 4)):
-        st = sv.sv_plan(n, dt, dense, sv.schedule(block_qubits=l, fuse_k=k))
-        assert st["fused"] > 0, (dt, k)
+        for circ in (g, layered):
+            a = sv.sv_plan(n, dt, circ, sv.schedule(block_qubits=l, fuse_k=5))
+            b = sv.sv_plan(n, dt, circ, sv.schedule(block_qubits=l, fuse_k=1))
+            assert a["fused"] == 0 and a["passes"] == b["passes"]
+    deep = {d: W.blocked_dense_circuit(n, 1, d, np.random.default_rng(d)) for d in (8, 12, 24)}
+    fused = lambda dt, d: sv.sv_plan(n, dt, deep[d], sv.schedule(block_qubits=l, fuse_k=5))["fused"]  # noqa: E731
+    assert fused("c128", 8) == 0 and fused("c128", 12) > 0
+    assert fused("c64", 12) == 0 and fused("c64", 24) > 0
     # the emulated programs of the gated windows match the oracle
     psi0 = np.random.default_rng(4).normal(size=1 << 14) + 0j
     psi0 /= np.linalg.norm(psi0)
-    dense14 = W.layered_dense_circuit(14, 6, np.random.default_rng(5))
-    for dtype, k, tol in ((1, 4, 1e-12), (0, 5, 1e-6)):
-        got, _ = run(14, dense14, psi0, dtype=dtype, l=12, fuse=k, policy=2)
-        assert np.max(np.abs(got - oracle.apply(14, dense14, psi0))) < tol
+    deep14 = W.blocked_dense_circuit(14, 1, 24, np.random.default_rng(5))
+    for dtype, k, tol in ((1, 5, 1e-12), (0, 5, 1e-6)):
+        got, _ = run(14, deep14, psi0, dtype=dtype, l=12, fuse=k, policy=2)
+        assert np.max(np.abs(got - oracle.apply(14, deep14, psi0))) < tol
 
 
 @pytest.mark.parametrize("policy", [1, 2])
