@@ -483,6 +483,8 @@ def main():
                     help="compile the sweep's passes into DIR on the host and exit (no GPU)")
     ap.add_argument("--only", choices=("batch", "dense-fusion"),
                     help="run only that section (batched QPE or dense-circuit fusion) and print its record")
+    ap.add_argument("--dense-depth", type=int, default=-1,
+                    help="with --only dense-fusion: only the circuit of this depth (0: layered)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 4 GiB read + 4 GiB write kernel "
                          "(the reference for HBM byte counters)")
@@ -503,9 +505,10 @@ def main():
 
         sv.load()
         torch.cuda.set_device(0)
-        rec = (bench_batch(args.steps) if args.only == "batch" else
-               bench_dense_fusion(args.steps, cases=(("layered-depth1", 0), ("blocked-depth8", 8),
-                                                     ("blocked-depth12", 12), ("blocked-depth24", 24))))
+        cases = (("layered-depth1", 0), ("blocked-depth8", 8), ("blocked-depth12", 12), ("blocked-depth24", 24))
+        if args.dense_depth >= 0:
+            cases = tuple(c for c in cases if c[1] == args.dense_depth)
+        rec = bench_batch(args.steps) if args.only == "batch" else bench_dense_fusion(args.steps, cases=cases)
         print(json.dumps(rec), flush=True)
         return
     if args.sweep:

@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
 #include <cstdlib>
 #include <vector>
 
@@ -26,6 +27,31 @@ using namespace svp;
 
 namespace {
 
+// Writes per amplitude in the current step (every kernel is checked to write
+// each amplitude it owns exactly once per step) and the steps that broke it.
+std::vector<uint32_t> g_writes;
+bool g_plant_double_write = false;  // tests: one block pass stores an amplitude twice
+int64_t g_write_faults = 0, g_writes_total = 0;
+
+void note_write(uint64_t i)
+{
+    g_writes[i] += 1;
+    g_writes_total += 1;
+}
+
+// After a step: every amplitude written exactly `expect(i)` times (0 or 1).
+template <class F>
+void check_writes(uint64_t N, F expect)
+{
+    for (uint64_t i = 0; i < N; ++i) {
+        if (g_writes[i] != expect(i)) {
+            ++g_write_faults;
+            break;
+        }
+    }
+    std::fill(g_writes.begin(), g_writes.end(), 0u);
+}
+
 void apply_pair_gate(std::vector<cd> &S, int n, const MGate &g)
 {
     const uint64_t N = 1ull << n;
@@ -37,6 +63,8 @@ void apply_pair_gate(std::vector<cd> &S, int n, const MGate &g)
         const cd a = S[j], b = S[k];
         S[j] = u00 * a + u01 * b;
         S[k] = u10 * a + u11 * b;
+        note_write(j);
+        note_write(k);
     }
 }
 
@@ -357,7 +385,12 @@ void run_k2(std::vector<cd> &S, int n, const Step &st, const Plan &plan)
             }
         }
         for (int tid = 0; tid < NT; ++tid)
-            for (int k = 0; k < R; ++k) S[amp_mem(tid, k)] = a[tid][k];
+            for (int k = 0; k < R; ++k) {
+                const uint64_t addr = amp_mem(tid, k);
+                S[addr] = a[tid][k];
+                note_write(addr);
+            }
+        if (g_plant_double_write && bid == 0) note_write(amp_mem(0, 0));  // planted mistake (tests)
     }
 }
 
@@ -389,18 +422,31 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
     const uint64_t N = 1ull << n;
     std::vector<cd> S(N);
     for (uint64_t i = 0; i < N; ++i) S[i] = cd(state_inout[2 * i], state_inout[2 * i + 1]);
+    g_writes.assign(N, 0u);
+    g_plant_double_write = std::getenv("EMU_PLANT_DOUBLE_WRITE") != nullptr;
+    g_write_faults = 0;
+    g_writes_total = 0;
     for (const Step &st : plan.steps) {
         if (st.kind == ST_K1) {
             apply_pair_gate(S, n, st.g);
+            // the pairs whose control holds, once each
+            const MGate g = st.g;
+            check_writes(N, [&](uint64_t i) { return (uint32_t)(g.c < 0 || ((i >> g.c) & 1ull)); });
         } else if (st.kind == ST_K3) {
             for (uint64_t i = 0; i < N; ++i) {
                 if (((i >> st.p) & 1ull) && !((i >> st.v) & 1ull)) {
                     const uint64_t k = i ^ (1ull << st.p) ^ (1ull << st.v);
                     std::swap(S[i], S[k]);
+                    note_write(i);
+                    note_write(k);
                 }
             }
+            // the exchanged pairs, once each
+            check_writes(N, [&](uint64_t i) { return (uint32_t)(((i >> st.p) ^ (i >> st.v)) & 1ull); });
         } else {
             run_k2(S, n, st, plan);
+            // a block pass stores every amplitude once
+            check_writes(N, [](uint64_t) { return 1u; });
         }
     }
     for (uint64_t x = 0; x < N; ++x) {
@@ -416,6 +462,8 @@ extern "C" int emu_apply(int n, int dtype, int mode, int l, int logr, int policy
     counts_out[3] = (int64_t)plan.table.size();
     counts_out[4] = 0;  // block passes that stage half the block
     for (const Step &st : plan.steps) counts_out[4] += st.kind == ST_K2 && st.half_lds;
+    counts_out[5] = g_write_faults;  // steps that wrote an amplitude other than once
+    counts_out[6] = g_writes_total;
     return 0;
 }
 

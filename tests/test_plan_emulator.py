@@ -56,12 +56,16 @@ def emu():
 def run(n, gates, state=None, dtype=0, mode=1, l=0, logr=4, policy=1, remap=0, diag_free=1,
         pin=-1, fuse=1):
     s = oracle.zero_state(n) if state is None else np.array(state, dtype=np.complex128)
-    counts = (ctypes.c_int64 * 5)()
+    counts = (ctypes.c_int64 * 8)()
     g = np.ascontiguousarray(gates)
     rc = emu().emu_apply(n, dtype, mode, l, logr, policy, remap, diag_free, pin, fuse,
                          g.ctypes.data if len(g) else None, len(g),
                          s.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), counts)
     assert rc == 0
+    # every step wrote each amplitude it owns exactly once (block passes:
+    # all of them; pair steps: the pairs whose control holds; exchanges: the
+    # exchanged pairs)
+    assert counts[5] == 0, "an emulated step wrote an amplitude other than once"
     return s, list(counts)
 
 
@@ -331,3 +335,16 @@ def test_graph_schedule_edge_cases(n, l, logr, pin, half, monkeypatch):
         psi0 /= np.linalg.norm(psi0)
         got, _ = run(n, g, psi0, l=l, logr=logr, policy=2, pin=pin)
         assert np.max(np.abs(got - oracle.apply(n, g, psi0))) < 1e-12
+
+
+def test_planted_double_write_is_caught(monkeypatch):
+    """The per-amplitude write count catches a block pass that stores an
+    amplitude twice (a mistake planted in the emulator)."""
+    n = 8
+    g = W.random_mixed_circuit(n, 30, np.random.default_rng(1))
+    s = oracle.zero_state(n)
+    counts = (ctypes.c_int64 * 8)()
+    monkeypatch.setenv("EMU_PLANT_DOUBLE_WRITE", "1")
+    rc = emu().emu_apply(n, 0, 1, 6, 4, 2, 0, 1, -1, 1, g.ctypes.data, len(g),
+                         s.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), counts)
+    assert rc == 0 and counts[0] > 0 and counts[5] > 0
