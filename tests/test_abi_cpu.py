@@ -77,11 +77,13 @@ def test_schedule_errors():
     assert e.value.status == sv.SV_ERR_INVALID_ARG
     # matrix-core windows need blocks of whole waves (2^(l - 4) >= 64 threads)
     assert sv.sv_plan(6, "c64", g, sv.schedule(fuse_k=5))["fused"] == 0
-    # the QPE's windows are too cheap for the matrix cores (cost gate); a
-    # layered dense circuit's are not
+    # the QPE's windows are too cheap for the matrix cores (cost gate), and
+    # so are a layered circuit's; deep dense runs inside 5-qubit groups are not
     assert sv.sv_plan(12, "c64", W.qpe_gates(12, 0.25), sv.schedule(fuse_k=5))["fused"] == 0
-    dense = W.layered_dense_circuit(12, 4, np.random.default_rng(0))
-    assert sv.sv_plan(12, "c64", dense, sv.schedule(fuse_k=5))["fused"] > 0
+    layered = W.layered_dense_circuit(12, 4, np.random.default_rng(0))
+    assert sv.sv_plan(12, "c64", layered, sv.schedule(fuse_k=5))["fused"] == 0
+    deep = W.blocked_dense_circuit(12, 1, 24, np.random.default_rng(0))
+    assert sv.sv_plan(12, "c64", deep, sv.schedule(fuse_k=5))["fused"] > 0
     with pytest.raises(sv.SvError) as e:
         sv.sv_plan(6, "c64", g, sv.schedule(block_qubits=15))
     assert e.value.status == sv.SV_ERR_UNSUPPORTED
