@@ -204,16 +204,16 @@ def test_batch_packs_small_instances_onto_shared_work_groups():
         s.close()
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_batch_with_matrix_core_windows(dtype):
-    """Dense layered circuits with fuse_k = 5: windows run through the
-    batched kernel's matrix-core build; every instance against the oracle."""
+@pytest.mark.parametrize("dtype,depth", [("c64", 24), ("c128", 12)])
+def test_batch_with_matrix_core_windows(dtype, depth):
+    """Deep dense runs inside 5-qubit groups with fuse_k = 5: the cost gate
+    admits windows, which run through the batched kernel's matrix-core
+    build; every instance against the oracle."""
     import oracle
-    rng = np.random.default_rng(48)
     ns = [12, 13, 14, 16]
-    gl = [W.layered_dense_circuit(n, 3, rng) for n in ns]
+    gl = [W.blocked_dense_circuit(n, 1, depth, np.random.default_rng(48 + n)) for n in ns]
     batch = make(ns, dtype)
-    log(f"case batch windows dtype={dtype}")
+    log(f"case batch windows dtype={dtype} depth={depth}")
     sched = sv.schedule(fuse_k=5)
     sv.sv_apply_batch([s.h for s in batch], gl, sched)
     fused = sum(s.stats()["fused"] for s in batch)
