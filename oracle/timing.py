@@ -13,6 +13,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import sys
 import time
 
 import numpy as np
@@ -93,6 +94,7 @@ def median_of_runs(n: int, gates, precision: str, runs: int = 3, pause_s: float 
         S = alloc_state(n, precision)
         times.append(time_gate_loop(n, gates, S, precision))
         del S
+        print(f"[oracle timing] n={n} {precision} run {r + 1}/{runs}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
     return float(np.median(times)), times
 
 
