@@ -518,22 +518,35 @@ __device__ __forceinline__ void k2_diagrun(C *a, const K2Ctx &cx, const svp::Dia
     // the order the record defines: a group whose top bit is not in k has
     // rmask outside k and is skipped for that slot.
     if constexpr (sizeof(C) * R <= 128) {
-        // each group's factor once per block, folded into every slot it covers
+        // Each group's factor once per block. Slot k with top bit b starts
+        // from the finished product of slot k - 2^b (the groups of lower
+        // levels that lie within k are exactly those within k - 2^b) and
+        // folds only the groups of level b that lie within k.
         C T[R];
         bool have[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            T[k] = mk<C>(1.0, 0.0);
-            have[k] = false;
+        T[0] = mk<C>(1.0, 0.0);
+        have[0] = false;
+        int i = 0;
+        for (; i < ng && gs[i].rmask == 0; ++i) {
+            T[0] = k2_fold(!have[0], T[0], k2_group_factor<C>(gs[i], cx));
+            have[0] = true;
         }
-        for (int i = 0; i < ng; ++i) {
-            const int rm = gs[i].rmask;
-            const C f = k2_group_factor<C>(gs[i], cx);
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                if (!((kmask >> k) & 1u) || (rm & ~k)) continue;
-                T[k] = k2_fold(!have[k], T[k], f);
-                have[k] = true;
+        for (int b = 0; b < LOGR; ++b) {
+#pragma unroll
+            for (int k = 1 << b; k < (2 << b); ++k) {
+                T[k] = T[k - (1 << b)];
+                have[k] = have[k - (1 << b)];
+            }
+            for (; i < ng && (31 - __builtin_clz((uint32_t)gs[i].rmask)) == b; ++i) {
+                const int rm = gs[i].rmask;
+                const C f = k2_group_factor<C>(gs[i], cx);
+#pragma unroll
+                for (int k = 1 << b; k < (2 << b); ++k) {
+                    if (rm & ~k) continue;
+                    T[k] = k2_fold(!have[k], T[k], f);
+                    have[k] = true;
+                }
             }
         }
 #pragma unroll
