@@ -35,7 +35,7 @@ namespace svq {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr size_t kMaxGates = size_t(1) << 26;
+constexpr size_t kMaxGates = size_t(1) << 24;  // 16 Mi records (3 GiB)
 constexpr int kMaxDepth = 64;
 
 enum TokKind { T_ID, T_NUM, T_STR, T_SYM, T_END };
