@@ -222,3 +222,28 @@ def test_batch_with_matrix_core_windows(dtype, depth):
     assert fused > 0
     for s in batch:
         s.close()
+
+
+def test_batch_on_a_capped_grid(monkeypatch):
+    """SV_BATCH_MAX_GRID = 6: the instances share six work-groups (large
+    ones as small groups meeting at their barriers, the rest packed several
+    to a work-group); results equal the single runs bit for bit."""
+    monkeypatch.setenv("SV_BATCH_MAX_GRID", "6")
+    rng = np.random.default_rng(49)
+    ns = [18, 17, 12, 13, 14, 12, 15, 16, 13, 12, 14]
+    phis = [float(x) for x in rng.random(len(ns))]
+    gl = [W.qpe_gates(n, p) for n, p in zip(ns, phis)]
+    batch = make(ns, "c64")
+    log("case batch capped grid")
+    sv.sv_apply_batch([s.h for s in batch], gl)
+    tb = launch_tbits("c64", ns)
+    for i, (n, p) in enumerate(zip(ns, phis)):
+        l = batch[i].stats()["block_qubits"]
+        single = sv.StateVector(n, "c64")
+        single.apply(gl[i], sv.schedule(block_qubits=l, reg_qubits=l - tb))
+        a, b = batch[i].state(), single.state()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (i, n, l)
+        assert np.max(np.abs(a - cf.qpe_state(n, p))) <= 2e-5
+        single.close()
+    for s in batch:
+        s.close()
