@@ -205,3 +205,28 @@ def test_invalid_records_leave_the_state_untouched():
             sv.ex_gates([("U", [0, 1], [], np.eye(2))])
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_qpe_written_in_openqasm(dtype):
+    """Section IV-A's QPE as an OpenQASM 2.0 program (22 qubits: counting
+    register c, eigen qubit e prepared in |1>, controlled powers of
+    P(2 pi phi) as controlled phases, inverse QFT), read by the library and
+    run through sv_apply_circuit_ex, against the closed-form state."""
+    from oracle import qpe as cf
+    t = 21
+    phi = 0.7071067811865476
+    lines = ['OPENQASM 2.0;', 'include "qelib1.inc";', f'qreg c[{t}];', 'qreg e[1];', 'x e[0];', 'h c;']
+    for j in range(t):
+        lines.append(f"cp(2*pi*{math.fmod(phi * (1 << j), 1.0)!r}) c[{j}], e[0];")
+    for q in range(t // 2):
+        lines.append(f"swap c[{q}], c[{t - 1 - q}];")
+    for q in range(t):
+        for p in range(q):
+            lines.append(f"cp(-pi/2^{q - p}) c[{p}], c[{q}];")
+        lines.append(f"h c[{q}];")
+    n, g = sv.sv_qasm_parse("\n".join(lines) + "\n")
+    assert n == t + 1
+    log(f"case qasm qpe dtype={dtype} gates={len(g)}")
+    got, _ = run_case(n, dtype, g)
+    assert np.max(np.abs(got - cf.qpe_state(n, phi))) <= TOL[dtype]
